@@ -1,0 +1,195 @@
+"""Benchmark: synaptic events delivered per second on one MI355X.
+
+A step is one slice of the simulation cycle (Sec. 1 / Sec. 2.1 of the
+paper): deliver the completed slice's spikes through the connection table
+into the ring buffers, then update every neuron through the next d_min
+steps with spike compaction -- one fused kernel launch.  The workload is the
+112,500-neuron alpha-current balanced random net at in-degree 11,250
+(1.27e9 synapses), run closed loop in its self-consistent state; both the
+FP32 form (9 B/synapse) and the BF16-residual form (5 B/synapse) are timed,
+the latter is the headline ``value``.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(events: float, spikes: float, n: int, d_min: int, b_syn: int,
+                      s_state: int) -> float:
+    """Bytes one slice must move: synapses of every delivered event, one ring
+    write and one read per neuron-step, neuron state read + write, and the
+    spike list (5 B per entry)."""
+    return events * b_syn + n * d_min * 8 + n * 2 * s_state + spikes * 5
+
+
+def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dict:
+    import torch
+
+    from paper_2109_12855_amd import sdeliver
+
+    t0 = time.time()
+    net = sdeliver.Net(cfg).build()
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    d_min = cfg["d_min"]
+    _log(f"{cfg['name']}: built {net.n_syn:.3e} synapses in {t_build:.1f} s")
+    net.simulate_steps(warmup * d_min)
+    torch.cuda.synchronize()
+    s0 = net.stats()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    net.simulate_steps(steps * d_min)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    s1 = net.stats()
+    events = s1["events_delivered"] - s0["events_delivered"]
+    spikes = s1["spikes_delivered"] - s0["spikes_delivered"]
+    emitted = s1["spikes_emitted"] - s0["spikes_emitted"]
+    # per-launch durations: an event pair around each slice launch, on the
+    # stream the kernel runs on (torch's current stream is the context's)
+    k_ms = None
+    if per_launch:
+        n_l = min(steps, 200)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_l)]
+        s2 = net.stats()
+        for a, b in evs:
+            a.record()
+            net.simulate_steps(d_min)
+            b.record()
+        torch.cuda.synchronize()
+        s3 = net.stats()
+        k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        ev_l = (s3["events_delivered"] - s2["events_delivered"]) / n_l
+        sp_l = (s3["spikes_delivered"] - s2["spikes_delivered"]) / n_l
+    n = net.n_local
+    b_syn = 9 if cfg["wform"] == 0 else 5
+    s_state = 16 if cfg["model"] == 1 else 8
+    b_alg = algorithmic_bytes(events / steps, spikes / steps, n, d_min, b_syn, s_state)
+    out = dict(
+        name=cfg["name"], build_s=round(t_build, 2), ms_total=ms, ms_per_step=ms / steps,
+        events_per_s=events / (ms * 1e-3), events_per_step=events / steps,
+        spikes_per_step=spikes / steps, rate_hz=emitted / (n * steps * d_min * cfg["h"] * 1e-3),
+        alg_bytes_per_step=b_alg, alg_gbs=b_alg / (ms / steps * 1e-3) / 1e9,
+    )
+    if k_ms is not None:
+        b_l = algorithmic_bytes(ev_l, sp_l, n, d_min, b_syn, s_state)
+        out.update(kernel_ms=k_ms, kernel_alg_bytes=b_l, kernel_gbs=b_l / (k_ms * 1e-3) / 1e9)
+    net.close()
+    del net
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cfg: dict, budget_s: float = 12.0, frac: int = 16) -> dict:
+    """The FP64 oracle on the host: delivery + update of a 1/frac target
+    sample of the same network, fed seeded synthetic spike lists at the
+    GPU run's spike count per slice."""
+    import oracle
+    from paper_2109_12855_amd import workloads
+
+    n = cfg["n_exc"] + cfg["n_inh"]
+    n_t = n // frac
+    t0 = time.time()
+    ref = oracle.Net(cfg, tgt_lo=0, tgt_hi=n_t)
+    _log(f"oracle sample built ({ref.n_syn:.2e} synapses) in {time.time() - t0:.1f} s")
+    d_min = cfg["d_min"]
+    spikes_per_slice = int(round(n * 8.0 * d_min * cfg["h"] * 1e-3))
+    events = 0
+    slices = 0
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s:
+        src, lag = workloads.replay_spikes(n, spikes_per_slice, d_min, seed=1000 + slices)
+        _, ne = ref.deliver(src, lag, ref.t_now - d_min if ref.t_now >= d_min else 0)
+        ref.update(d_min)
+        events += ne
+        slices += 1
+    dt = time.perf_counter() - t_start
+    return {"value": events / dt, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_t} of {n} targets (all sources), {slices} slices of "
+                      f"{spikes_per_slice} spikes, FP64 deliver+update, single thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed slices (1 ms each)")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--forms", default="fp32,bf16_resid")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2109_12855_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    base = workloads.ALPHA_112K
+    forms = {"fp32": dict(base, wform=0, name="alpha_112500_fp32"),
+             "bf16_resid": dict(base, wform=2, name="alpha_112500_bf16_resid")}
+    res = {}
+    for f in args.forms.split(","):
+        _log(f"form {f}")
+        res[f] = run_form(forms[f], args.steps, args.warmup)
+        _log(json.dumps(res[f]))
+    head = res.get("bf16_resid") or next(iter(res.values()))
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(dict(base, wform=0))
+    roof = None
+    if "kernel_ms" in head:
+        roof = {"bound": "hbm", "achieved": round(head["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": None}
+    line = {
+        "metric": "synaptic events delivered/s",
+        "value": head["events_per_s"],
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "alpha_112500_k11250_closed_loop", "neurons": 112500,
+                   "in_degree": 11250, "synapses": 112500 * 11250, "slice_ms": 1.0,
+                   "weight_storage": "bf16_residual" if head is res.get("bf16_resid") else "fp32",
+                   "parallelism": "single_gpu"},
+        "achieved_alg_gbs": head["alg_gbs"],
+        "forms": res,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * sdeliver.h -- C ABI of the MI355X spike-delivery library.
+ *
+ * The library runs the hot path of a time-driven spiking-network simulation
+ * on one gfx950 GPU (Pronold et al., arXiv 2109.12855):
+ *   - build_connections: the network is created once from probabilistic
+ *     rules before simulation; its construction is not part of simulation
+ *     time (Sec. 1, Sec. 2.2).
+ *   - update_neurons: neurons advance on the h grid by the exact
+ *     propagators of their linear subthreshold dynamics (Sec. 1, Sec. 2.1).
+ *   - deliver_spikes: every spike's target segment is walked and each
+ *     synapse's weight is added into its target's ring buffer at the
+ *     synapse's delay, with the result Alg. REF defines (Sec. 3.1, 3.2).
+ *   - simulate(T): the cycle update -> (exchange) -> deliver repeats every
+ *     min-delay interval (Sec. 1, Sec. 2.1).
+ *
+ * Conventions for every call:
+ *   - Return value: SD_OK or a negative sd_status; nothing throws across the
+ *     ABI.  sd_last_error(ctx) holds a message for the last failure.
+ *   - Streams: all device work is ordered on the HIP stream given at
+ *     sd_create.  Calls that return host data synchronise that stream.
+ *   - Pointers: "d_" arguments are device pointers, "h_" are host pointers;
+ *     both are borrowed for the duration of the call (device pointers until
+ *     the stream reaches the call).
+ *   - Devices: a context lives on the device that was current at sd_create.
+ *   - Threads: one host thread at a time per context.
+ *   - Units: times in ms, steps as int64, weights in mV (delta model) or
+ *     pA (alpha model).
+ */
+#ifndef SDELIVER_H
+#define SDELIVER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sd_ctx sd_ctx;
+
+typedef enum {
+  SD_OK = 0,
+  SD_EINVAL = -1,        /* invalid argument or configuration                */
+  SD_ENOMEM = -2,        /* device allocation failed / arena too small       */
+  SD_EHIP = -3,          /* a HIP runtime call failed                        */
+  SD_EOVERFLOW = -4,     /* a device-side capacity was exceeded (sticky)     */
+  SD_ESTATE = -5,        /* call not valid in the context's current state    */
+  SD_EUNSUPPORTED = -6   /* configuration outside what this build supports   */
+} sd_status;
+
+typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
+
+/* Storage form of a synapse (weight, target, delay):
+ *   SD_W_FP32       f32 weight, i32 target id, u8 delay       (9 B / synapse)
+ *   SD_W_BF16       bf16 weight, u16 offset in block, u8 delay (5 B)
+ *   SD_W_BF16_RESID bf16 residual d, w = mu_pop * (1 + d),
+ *                   u16 offset in block, u8 delay              (5 B)      */
+typedef enum { SD_W_FP32 = 0, SD_W_BF16 = 1, SD_W_BF16_RESID = 2 } sd_wform;
+
+typedef struct {
+  int32_t model;             /* sd_model                                        */
+  int32_t wform;             /* sd_wform                                        */
+  int64_t n_exc, n_inh;      /* local neurons: E ids [0,n_exc), I ids after     */
+  int64_t n_src_exc;         /* open loop: virtual E sources (0 = closed loop)  */
+  int64_t n_src_inh;         /* open loop: virtual I sources                    */
+  int32_t k_exc, k_inh;      /* fixed in-degree, drawn with replacement         */
+  int32_t d_lo, d_hi;        /* delays uniform over [d_lo, d_hi] steps          */
+  int32_t d_min, d_max;      /* network min/max delay; a slice is d_min steps   */
+  int32_t ring_len;          /* ring buffer length L >= d_min + d_max, <= 64    */
+  double h;                  /* resolution (ms)                                 */
+  double w_exc, w_cv, g;     /* E weight mean and CV; I weight = -g * E draw    */
+  double tau_m, c_m, tau_syn, e_l, v_th, v_reset, t_ref, i_e;
+  double v0_lo, v0_hi;       /* initial V uniform in [v0_lo, v0_hi)             */
+  double drive_rate_hz;      /* independent Poisson drive per neuron            */
+  double drive_w;            /* weight of one drive event                       */
+  double src_rate_hz;        /* open loop: rate of each virtual source          */
+  uint64_t seed;
+  int32_t block_neurons;     /* target block size (0 = automatic)               */
+  int32_t record_spikes;     /* keep a device raster of emitted spikes (0/1)    */
+  int64_t record_cap;        /* raster capacity in spikes (0 = automatic)       */
+} sd_config;
+
+typedef struct {
+  int64_t n_local;           /* neurons held                                    */
+  int64_t n_src;             /* source ids (local, or virtual in open loop)     */
+  int64_t n_syn;             /* synapses                                        */
+  int32_t block_neurons;     /* target block size in use                        */
+  int32_t n_blocks;          /* number of target blocks                         */
+  int64_t table_bytes;       /* synapse arrays + segment pointers               */
+  int64_t arena_bytes;       /* total device memory of a context                */
+  int32_t bytes_per_synapse; /* 9 (FP32 form) or 5 (BF16 forms)                 */
+} sd_sizes;
+
+typedef struct {
+  int64_t t_now;             /* next step to update                             */
+  int64_t spikes_emitted;    /* local spikes since creation                     */
+  int64_t events_delivered;  /* synaptic events (sum of segment lengths)        */
+  int64_t spikes_delivered;  /* spike entries delivered                          */
+  int64_t slices;            /* fused slice launches                            */
+  int64_t spikes_recorded;   /* entries in the raster                           */
+  int32_t overflow;          /* sticky device overflow flags                    */
+} sd_stats;
+
+/* Sizes the context needs for this configuration (no device work). */
+sd_status sd_query_sizes(const sd_config* cfg, sd_sizes* out);
+
+/* Create a context on the current device, ordered on hip_stream (NULL: the
+ * null stream).  d_arena (optional) is caller-owned device memory of at least
+ * sizes.arena_bytes that the context carves all its buffers from and never
+ * frees; with d_arena NULL the context allocates (hipMalloc) and frees it.
+ * Computes the exact propagators in FP64 on the device, the weight quantile
+ * table and Poisson-drive thresholds on the host, and the initial state. */
+sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_t arena_bytes,
+                    sd_ctx** out);
+void sd_destroy(sd_ctx* ctx);
+const char* sd_last_error(const sd_ctx* ctx);
+
+/* Draw the network (one counter-based Philox4x64-10 block per synapse,
+ * target-major) and lay it out source-major per target block: for source s
+ * and block b the synapses targeting b form one contiguous segment, in
+ * (target, draw index) order.  Deterministic; run once before updates. */
+sd_status sd_build_connections(sd_ctx* ctx);
+
+/* Advance every neuron by n_steps (1 <= n_steps, and the steps must stay in
+ * the current slice of d_min steps): reads and consumes the ring buffer
+ * rows of those steps, draws the Poisson drive, propagates exactly, applies
+ * threshold/reset/refractoriness, and appends emitted spikes to the open
+ * slice's spike list (ordered by (lag, target block, neuron)). */
+sd_status sd_update_neurons(sd_ctx* ctx, int32_t n_steps);
+
+/* Deliver spikes (Alg. REF result): for every spike (src, lag) and every
+ * synapse (src -> j, delay d, weight w): ring[t0 + lag + d][j] += w.
+ * d_src/d_lag: n device entries, lag in [0, d_min), src < n_src.  With
+ * d_src == NULL the context's own completed slice is delivered and t0 is
+ * ignored.  Arrival steps must lie in [t_now, t_now + ring_len). */
+sd_status sd_deliver_spikes(sd_ctx* ctx, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
+                            int64_t t0);
+
+/* Run round(t_ms / h) steps of the full cycle with fused slice launches
+ * (deliver the completed slice, then update the next one).  Resumable:
+ * results do not depend on how a run is split into calls. */
+sd_status sd_simulate(sd_ctx* ctx, double t_ms);
+sd_status sd_simulate_steps(sd_ctx* ctx, int64_t n_steps);
+
+/* Validation mode: deliver 1.0 for every synapse so the ring holds exact
+ * per-cell event counts (0 = weights, 1 = counts). */
+sd_status sd_set_count_mode(sd_ctx* ctx, int32_t on);
+
+/* Open loop: precompute the virtual sources' spikes for steps
+ * [t_now, t_now + n_steps) (outside any timed region). */
+sd_status sd_prepare_input(sd_ctx* ctx, int64_t n_steps);
+
+/* --- read-back (synchronising) --------------------------------------------- */
+int64_t sd_t_now(const sd_ctx* ctx);
+sd_status sd_get_sizes(const sd_ctx* ctx, sd_sizes* out);
+sd_status sd_get_stats(sd_ctx* ctx, sd_stats* out);
+/* ring rows for steps [t_now, t_now + n_slots) into h_out[n_slots][n_local] */
+sd_status sd_read_ring(sd_ctx* ctx, float* h_out, int32_t n_slots);
+/* neuron state (any pointer may be NULL) */
+sd_status sd_read_state(sd_ctx* ctx, float* h_v, float* h_y1, float* h_y2, int32_t* h_r);
+sd_status sd_write_state(sd_ctx* ctx, const float* h_v, const float* h_y1, const float* h_y2,
+                         const int32_t* h_r);
+/* drain the raster: (step, neuron) pairs in emission-slice order */
+sd_status sd_get_spikes(sd_ctx* ctx, int64_t* h_step, uint32_t* h_id, int64_t cap, int64_t* n);
+/* spikes of the open (not yet delivered) slice */
+sd_status sd_get_pending(sd_ctx* ctx, uint32_t* h_src, uint8_t* h_lag, int64_t cap, int64_t* n,
+                         int64_t* slice_t0);
+/* connection table in canonical (source, target, draw) order, decoded:
+ * h_row[n_src+1] (int64), h_tgt[n_syn], h_dly[n_syn], h_w[n_syn] */
+sd_status sd_export_connections(sd_ctx* ctx, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
+                                float* h_w);
+/* segment pointers of one source over all blocks: h_ptr[n_blocks+1] */
+sd_status sd_export_segments(sd_ctx* ctx, int64_t src, int64_t* h_ptr);
+/* the synapses into target block b, source-major: h_row[n_src+1] (relative
+ * to the block's first synapse), then h_tgt/h_dly/h_w of *n_out synapses
+ * (h_tgt == NULL: only h_row and *n_out are written) */
+sd_status sd_export_block(sd_ctx* ctx, int32_t b, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
+                          float* h_w, int64_t* n_out);
+/* host-side tables as used by the device: w_e/w_i[65536] (decoded FP32),
+ * thr[64] Poisson thresholds (returns count in *n_thr), prop[7] FP64
+ * propagators computed on the device {P11,P21,P22,P31,P32,P33,P30}, and
+ * prop32[7] their FP32 roundings used by the update */
+sd_status sd_get_tables(sd_ctx* ctx, float* h_we, float* h_wi, uint32_t* h_thr, int32_t* n_thr,
+                        double* h_prop, float* h_prop32);
+/* the host-side tables alone, without a context or device:
+ * w_e/w_i[65536] decoded FP32 weights, thr[64] Poisson thresholds */
+sd_status sd_host_tables(const sd_config* cfg, float* h_we, float* h_wi, uint32_t* h_thr,
+                         int32_t* n_thr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

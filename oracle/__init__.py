@@ -118,6 +118,7 @@ def lib():
         L.or_open_loop_spikes.argtypes = [P(Config), C.c_int64, C.c_int32, C.c_void_p,
                                           C.c_void_p, C.c_int64]
         L.or_open_loop_spikes.restype = C.c_int64
+        L.or_read_vpre.argtypes = [C.c_void_p, C.c_void_p]
         L.or_drive_count.argtypes = [C.c_void_p, C.c_int64, C.c_int64]
         L.or_drive_count.restype = C.c_int32
         _lib = L
@@ -292,6 +293,11 @@ class Net:
         t0 = C.c_int64()
         n = lib().or_pending(self._h, _ptr(src), _ptr(lag), cap, C.byref(t0))
         return src[:n].copy(), lag[:n].copy(), t0.value
+
+    def vpre(self) -> np.ndarray:
+        out = np.zeros(self.n_local, np.float64)
+        lib().or_read_vpre(self._h, _ptr(out))
+        return out
 
     def drive_count(self, j: int, t: int) -> int:
         return lib().or_drive_count(self._h, int(j), int(t))

@@ -230,6 +230,7 @@ struct or_net {
   int n_thr;
   int32_t ref_steps;
   double *V, *y1, *y2;
+  double* vpre;             /* V before the threshold test, last step        */
   int32_t* r;
   double* rb;               /* [L][n_local]                                  */
   uint32_t* cnt;            /* [L][n_local] events per cell                  */
@@ -253,7 +254,7 @@ void or_net_destroy(or_net* n) {
   if (!n) return;
   free(n->tm_src); free(n->tm_dly); free(n->tm_widx);
   free(n->row); free(n->tgt); free(n->dly); free(n->w);
-  free(n->V); free(n->y1); free(n->y2); free(n->r);
+  free(n->V); free(n->y1); free(n->y2); free(n->r); free(n->vpre);
   free(n->rb); free(n->cnt); free(n->pend_src); free(n->pend_lag);
   free(n);
 }
@@ -339,6 +340,7 @@ or_net* or_net_create(const or_config* cfg) {
   n->y1 = (double*)calloc(nl, sizeof(double));
   n->y2 = (double*)calloc(nl, sizeof(double));
   n->r = (int32_t*)calloc(nl, sizeof(int32_t));
+  n->vpre = (double*)calloc(nl, sizeof(double));
   for (int64_t jl = 0; jl < n->n_local; ++jl) {
     uint64_t r[4];
     philox(c->seed, OR_STREAM_INIT, (uint64_t)(n->lo + jl), 0, r);
@@ -450,6 +452,7 @@ static int64_t update_steps(or_net* n, int64_t m, int to_pending, int64_t* spk_s
         n->y2[jl] = P21 * y1 + P22 * y2;
         n->y1[jl] = P11 * y1 + in_scale * (in + drive);
       }
+      n->vpre[jl] = V;
       if (V >= c->v_th) {
         V = c->v_reset;
         n->r[jl] = n->ref_steps;
@@ -541,6 +544,10 @@ void or_read_rb(const or_net* n, double* out, int64_t n_slots) {
   for (int64_t s = 0; s < n_slots; ++s)
     for (int64_t jl = 0; jl < n->n_local; ++jl)
       out[s * n->n_local + jl] = n->rb[((n->t_now + s) % L) * n->n_local + jl];
+}
+
+void or_read_vpre(const or_net* n, double* out) {
+  memcpy(out, n->vpre, sizeof(double) * (size_t)n->n_local);
 }
 
 void or_read_counts(const or_net* n, uint32_t* out, int64_t n_slots) {

@@ -1,0 +1,1052 @@
+// sd_api.cpp -- host side of the spike-delivery library (C ABI in
+// include/sdeliver.h): configuration checks, device arena, host tables,
+// the slice state machine and read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sdeliver.h"
+#include "sd_internal.h"
+
+using namespace sd;
+
+// ---------------------------------------------------------------------------
+// host tables
+// ---------------------------------------------------------------------------
+namespace {
+
+// Inverse normal CDF by Wichura's AS 241 (PPND16, Appl. Statist. 37, 1988):
+// a degree-7/7 rational function in r = 0.180625 - q^2 for |q| <= 0.425
+// and in s = sqrt(-log(min(p, 1-p))) shifted by 1.6 (s <= 5) or 5 beyond.
+struct Rational77 {
+  double num[8];
+  double den[8];  // den[0] == 1
+  double eval(double x) const {
+    double n = 0.0, d = 0.0;
+    for (int i = 7; i >= 0; --i) {
+      n = n * x + num[i];
+      d = d * x + den[i];
+    }
+    return n / d;
+  }
+};
+
+constexpr Rational77 kCentral = {
+    {3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
+     1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
+     3.3430575583588128105e+4, 2.5090809287301226727e+3},
+    {1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3,
+     2.1213794301586595867e+4, 3.9307895800092710610e+4, 2.8729085735721942674e+4,
+     5.2264952788528545610e+3}};
+constexpr Rational77 kNear = {
+    {1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
+     3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
+     2.27238449892691845833e-2, 7.74545014278341407640e-4},
+    {1.0, 2.05319162663775882187e0, 1.67638483018380384940e0, 6.89767334985100004550e-1,
+     1.48103976427480074590e-1, 1.51986665636164571966e-2, 5.47593808499534494600e-4,
+     1.05075007164441684324e-9}};
+constexpr Rational77 kFar = {
+    {6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
+     2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
+     2.71155556874348757815e-5, 2.01033439929228813265e-7},
+    {1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2,
+     7.86869131145613259100e-4, 1.84631831751005468180e-5, 1.42151175831644588870e-7,
+     2.04426310338993978564e-15}};
+
+double inv_normal_cdf(double p) {
+  const double q = p - 0.5;
+  if (std::fabs(q) <= 0.425) return q * kCentral.eval(0.180625 - q * q);
+  const double tail = q < 0.0 ? p : 1.0 - p;
+  const double s = std::sqrt(-std::log(tail));
+  const double v = s <= 5.0 ? kNear.eval(s - 1.6) : kFar.eval(s - 5.0);
+  return q < 0.0 ? -v : v;
+}
+
+uint16_t bf16_bits_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t rounded = u + 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(rounded >> 16);
+}
+
+// residual BF16 code of an FP32 weight: d = bf16(fp32(w / mu - 1))
+uint16_t resid_bits(float w, float mu) {
+  return bf16_bits_rne((float)((double)w / (double)mu - 1.0));
+}
+
+// Poisson(lambda) CDF thresholds scaled to 2^32 (floor), truncated where the
+// scaled CDF reaches 2^32 - 1.
+int poisson_table(double lambda, uint32_t* out, int cap) {
+  int n = 0;
+  double term = std::exp(-lambda);
+  double cdf = term;
+  for (int k = 0; n < cap; ++k) {
+    if (k > 0) {
+      term *= lambda / k;
+      cdf += term;
+    }
+    const double scaled = std::floor(cdf * 4294967296.0);
+    if (scaled >= 4294967295.0) break;
+    out[n++] = (uint32_t)scaled;
+  }
+  return n;
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// FP32 weight of quantile cell i: mu (1 + cv z_i), z_i = Phi^-1((i + 1/2) / 2^16);
+// the inhibitory table is -g times the same draw.
+void quantile_weights(const sd_config& g, float* we, float* wi) {
+  for (int i = 0; i < 65536; ++i) {
+    const double z = inv_normal_cdf((i + 0.5) / 65536.0);
+    const double w = g.w_exc * (1.0 + g.w_cv * z);
+    we[i] = (float)w;
+    wi[i] = (float)(-g.g * w);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct sd_ctx {
+  sd_config cfg;
+  sd_sizes sz;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool own_arena = false;
+  char* arena = nullptr;
+  std::string err;
+  // geometry
+  int64_t N = 0, n_src = 0, n_syn = 0, src_e_end = 0;
+  int32_t B = 0, NB = 0, K = 0, grid_per_xcd = 0, out_cap = 0;
+  int64_t M = 0;  // entries of the segment-pointer table
+  // device buffers
+  uint32_t* row = nullptr;
+  uint32_t* cursor = nullptr;
+  uint32_t* tile_sums = nullptr;
+  int64_t n_tiles = 0;
+  void* syn_tgt = nullptr;
+  uint8_t* syn_dly = nullptr;
+  void* syn_w = nullptr;
+  float *V = nullptr, *y1 = nullptr, *y2 = nullptr;
+  int32_t* r = nullptr;
+  float* rb = nullptr;
+  uint32_t* list[2] = {nullptr, nullptr};
+  int32_t* list_cnt[2] = {nullptr, nullptr};
+  uint2* rec = nullptr;
+  int64_t rec_cap = 0;
+  void* wtab_e = nullptr;
+  void* wtab_i = nullptr;
+  uint32_t* thr = nullptr;
+  double* prop64 = nullptr;
+  float* prop32 = nullptr;
+  unsigned long long* counters = nullptr;  // ev, spk_in, spk, rec_n
+  int32_t* overflow = nullptr;
+  // open-loop input schedule
+  uint32_t* in_list = nullptr;
+  int64_t* in_off = nullptr;     // device, per slice
+  int32_t* in_cnt = nullptr;     // device, per slice
+  std::vector<int64_t> in_off_h;
+  int64_t in_t0 = 0, in_slices = 0;
+  // host copies of tables
+  std::vector<float> we_h, wi_h;
+  uint32_t thr_h[kMaxThr];
+  int32_t n_thr = 0;
+  float mu_e = 0.f, mu_i = 0.f;
+  int32_t ref_steps = 0;
+  // state machine
+  bool built = false;
+  int64_t t_now = 0;
+  int64_t rb_hi = 0;
+  bool pend_open = false;   // a slice has spikes not yet delivered
+  int64_t pend_t0 = 0;      // start step of that slice
+  int cur = 0;              // list buffer holding the open slice
+  int32_t count_mode = 0;
+  int64_t slices = 0;
+  int64_t rec_read = 0;     // raster entries already drained
+};
+
+namespace {
+
+sd_status fail(sd_ctx* c, sd_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(ctx, call)                                                         \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, SD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+bool open_loop(const sd_config& c) { return c.n_src_exc > 0; }
+
+int32_t auto_block(const sd_config& c, int64_t N) {
+  if (c.block_neurons > 0) return c.block_neurons;
+  // one block per compute unit, 64-aligned, at least one wave of neurons
+  int64_t b = (N + 255) / 256;
+  b = (b + 63) / 64 * 64;
+  if (b < 64) b = 64;
+  return (int32_t)b;
+}
+
+sd_status check_config(const sd_config* c, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return SD_EINVAL;
+  };
+  if (!c) return bad("null config");
+  if (c->model != SD_IAF_PSC_DELTA && c->model != SD_IAF_PSC_ALPHA) return bad("unknown model");
+  if (c->wform < SD_W_FP32 || c->wform > SD_W_BF16_RESID) return bad("unknown weight form");
+  if (c->n_exc < 0 || c->n_inh < 0 || c->n_exc + c->n_inh <= 0) return bad("empty network");
+  if (c->k_exc < 0 || c->k_inh < 0) return bad("negative in-degree");
+  if (c->k_exc > 0 && (open_loop(*c) ? c->n_src_exc : c->n_exc) <= 0) return bad("no E sources");
+  if (c->k_inh > 0 && (open_loop(*c) ? c->n_src_inh : c->n_inh) <= 0) return bad("no I sources");
+  if (c->d_min < 1 || c->d_min > 31) return bad("d_min must be in [1, 31]");
+  if (c->d_lo < c->d_min || c->d_hi < c->d_lo || c->d_hi > c->d_max || c->d_max > 255)
+    return bad("delays must satisfy d_min <= d_lo <= d_hi <= d_max <= 255");
+  if (c->ring_len < c->d_min + c->d_max || c->ring_len > 512) return bad("ring_len out of range");
+  if (!(c->h > 0.0) || !(c->tau_m > 0.0) || !(c->c_m > 0.0)) return bad("non-positive h/tau/C");
+  if (c->model == SD_IAF_PSC_ALPHA && (!(c->tau_syn > 0.0) || c->tau_syn == c->tau_m))
+    return bad("alpha model needs tau_syn > 0 and tau_syn != tau_m");
+  if (c->t_ref < 0.0 || c->drive_rate_hz < 0.0 || c->src_rate_hz < 0.0) return bad("negative rate");
+  if (c->block_neurons < 0 || (c->block_neurons % 64) != 0) return bad("block_neurons % 64 != 0");
+  if (c->w_cv < 0.0) return bad("negative weight CV");
+  return SD_OK;
+}
+
+// Everything sizes-related in one place, shared by query and create.
+struct Layout {
+  sd_sizes sz;
+  int64_t N, n_src, n_syn, M, n_tiles, rec_cap;
+  int32_t B, NB, out_cap, bps_w, bps_t;
+  size_t off_row, off_cursor, off_tiles, off_tgt, off_dly, off_w, off_V, off_y1, off_y2, off_r,
+      off_rb, off_list0, off_list1, off_cnt0, off_cnt1, off_rec, off_wte, off_wti, off_thr,
+      off_p64, off_p32, off_counters, off_overflow, total;
+};
+
+sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
+  sd_status s = check_config(c, why);
+  if (s != SD_OK) return s;
+  L->N = c->n_exc + c->n_inh;
+  L->n_src = open_loop(*c) ? c->n_src_exc + c->n_src_inh : L->N;
+  const int64_t K = (int64_t)c->k_exc + c->k_inh;
+  L->n_syn = L->N * K;
+  L->B = auto_block(*c, L->N);
+  L->NB = (int32_t)((L->N + L->B - 1) / L->B);
+  if (L->B > 65536 && c->wform != SD_W_FP32) {
+    *why = "u16 offsets need blocks of at most 65536 neurons";
+    return SD_EINVAL;
+  }
+  const size_t lds = slice_lds_bytes(L->B, c->d_min, c->d_max, L->NB);
+  if (lds > 160 * 1024) {
+    *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
+    return SD_EUNSUPPORTED;
+  }
+  L->M = L->n_src * L->NB + 1;
+  if (L->n_syn >= (int64_t)UINT32_MAX || L->N >= (1LL << 27) || L->n_src >= (1LL << 27)) {
+    *why = "more than 2^32 synapses or 2^27 neurons needs the sparse layout";
+    return SD_EUNSUPPORTED;
+  }
+  L->n_tiles = (L->M + 4095) / 4096;
+  L->out_cap = L->B * c->d_min;
+  L->rec_cap = c->record_spikes ? (c->record_cap > 0 ? c->record_cap
+                                                     : std::max<int64_t>(1 << 20, L->N * 64))
+                                : 0;
+  L->bps_w = c->wform == SD_W_FP32 ? 4 : 2;
+  L->bps_t = c->wform == SD_W_FP32 ? 4 : 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L->off_row = take((size_t)L->M * 4);
+  L->off_cursor = take((size_t)L->M * 4);
+  L->off_tiles = take((size_t)L->n_tiles * 4);
+  L->off_tgt = take((size_t)L->n_syn * L->bps_t);
+  L->off_dly = take((size_t)L->n_syn);
+  L->off_w = take((size_t)L->n_syn * L->bps_w);
+  L->off_V = take((size_t)L->N * 4);
+  L->off_y1 = take((size_t)L->N * 4);
+  L->off_y2 = take((size_t)L->N * 4);
+  L->off_r = take((size_t)L->N * 4);
+  L->off_rb = take((size_t)c->ring_len * L->N * 4);
+  L->off_list0 = take((size_t)L->NB * L->out_cap * 4);
+  L->off_list1 = take((size_t)L->NB * L->out_cap * 4);
+  L->off_cnt0 = take((size_t)L->NB * 4);
+  L->off_cnt1 = take((size_t)L->NB * 4);
+  L->off_rec = take((size_t)std::max<int64_t>(L->rec_cap, 1) * 8);
+  L->off_wte = take(65536 * 4);
+  L->off_wti = take(65536 * 4);
+  L->off_thr = take(kMaxThr * 4);
+  L->off_p64 = take(8 * 8);
+  L->off_p32 = take(8 * 4);
+  L->off_counters = take(8 * 8);
+  L->off_overflow = take(4);
+  L->total = o;
+  sd_sizes& z = L->sz;
+  z.n_local = L->N;
+  z.n_src = L->n_src;
+  z.n_syn = L->n_syn;
+  z.block_neurons = L->B;
+  z.n_blocks = L->NB;
+  z.bytes_per_synapse = c->wform == SD_W_FP32 ? 9 : 5;
+  z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * 4;
+  z.arena_bytes = (int64_t)L->total;
+  return SD_OK;
+}
+
+sd_status launch_slice_checked(sd_ctx* c, const SliceArgs& a) {
+  HIP_TRY(c, launch_slice(c->stream, a, c->cfg.wform));
+  return SD_OK;
+}
+
+SliceArgs base_args(sd_ctx* c) {
+  SliceArgs a;
+  std::memset(&a, 0, sizeof a);
+  const sd_config& g = c->cfg;
+  a.row = c->row;
+  a.syn_tgt = c->syn_tgt;
+  a.syn_dly = c->syn_dly;
+  a.syn_w = c->syn_w;
+  a.N = c->N;
+  a.NB = c->NB;
+  a.B = c->B;
+  a.Dmin = g.d_min;
+  a.Dmax = g.d_max;
+  a.L = g.ring_len;
+  a.src_e_end = c->src_e_end;
+  a.mu_e = c->mu_e;
+  a.mu_i = c->mu_i;
+  a.count_mode = c->count_mode;
+  a.grid_per_xcd = c->grid_per_xcd;
+  a.V = c->V;
+  a.y1 = c->y1;
+  a.y2 = c->y2;
+  a.r = c->r;
+  a.prop = c->prop32;
+  a.thr = c->thr;
+  a.n_thr = c->n_thr;
+  a.seed = g.seed;
+  a.e_l = (float)g.e_l;
+  a.v_th = (float)g.v_th;
+  a.v_reset = (float)g.v_reset;
+  a.drive_w = (float)g.drive_w;
+  a.ref_steps = c->ref_steps;
+  a.model = g.model;
+  a.rb = c->rb;
+  a.rb_hi = c->rb_hi;
+  a.write_list = open_loop(g) ? 0 : 1;
+  a.out_cap = c->out_cap;
+  a.rec = c->rec_cap > 0 ? c->rec : nullptr;
+  a.rec_n = c->counters + 3;
+  a.rec_cap = c->rec_cap;
+  a.ev_count = c->counters + 0;
+  a.spk_in_count = c->counters + 1;
+  a.spk_count = c->counters + 2;
+  a.overflow = c->overflow;
+  return a;
+}
+
+// Rows of steps in [max(t_now, rb_hi), w_lo) would be claimed valid by a
+// delivery window starting at w_lo without having been written: zero them.
+sd_status fill_gap(sd_ctx* c, int64_t w_lo) {
+  const int64_t lo = std::max(c->t_now, c->rb_hi);
+  if (w_lo > lo) {
+    HIP_TRY(c, launch_zero_rows(c->stream, c->rb, c->N, c->cfg.ring_len, lo, w_lo));
+    c->rb_hi = w_lo;
+  }
+  return SD_OK;
+}
+
+// Point the delivery arguments at the completed slice's spikes: the
+// context's own block lists (closed loop) or the prepared input (open loop).
+sd_status set_pending_input(sd_ctx* c, SliceArgs& a) {
+  if (open_loop(c->cfg)) {
+    const int64_t k = (c->pend_t0 - c->in_t0) / c->cfg.d_min;
+    if (!c->in_list || c->pend_t0 < c->in_t0 || k >= c->in_slices)
+      return fail(c, SD_ESTATE, "open-loop input not prepared for step %lld",
+                  (long long)c->pend_t0);
+    a.n_regions = 1;
+    a.in_list = c->in_list + c->in_off_h[k];
+    a.in_cnt = c->in_cnt + k;
+    a.in_cap = 0;
+  } else {
+    a.n_regions = c->NB;
+    a.in_list = c->list[c->cur];
+    a.in_cnt = c->list_cnt[c->cur];
+    a.in_cap = c->out_cap;
+  }
+  return SD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+sd_status sd_query_sizes(const sd_config* cfg, sd_sizes* out) {
+  Layout L;
+  std::string why;
+  sd_status s = make_layout(cfg, &L, &why);
+  if (s != SD_OK) return s;
+  if (out) *out = L.sz;
+  return SD_OK;
+}
+
+sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_t arena_bytes,
+                    sd_ctx** out) {
+  if (!out) return SD_EINVAL;
+  *out = nullptr;
+  sd_ctx* c = new sd_ctx();
+  Layout L;
+  sd_status s = make_layout(cfg, &L, &c->err);
+  if (s != SD_OK) {
+    *out = c;  // keep the message readable; caller destroys
+    return s;
+  }
+  c->cfg = *cfg;
+  c->sz = L.sz;
+  c->stream = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipGetDevice(&c->device));
+  c->N = L.N;
+  c->n_src = L.n_src;
+  c->n_syn = L.n_syn;
+  c->B = L.B;
+  c->NB = L.NB;
+  c->K = cfg->k_exc + cfg->k_inh;
+  c->M = L.M;
+  c->n_tiles = L.n_tiles;
+  c->out_cap = L.out_cap;
+  c->rec_cap = L.rec_cap;
+  c->grid_per_xcd = (L.NB + 7) / 8;
+  c->src_e_end = open_loop(*cfg) ? cfg->n_src_exc : cfg->n_exc;
+  *out = c;
+  if (d_arena) {
+    if (arena_bytes < L.total) return fail(c, SD_ENOMEM, "arena of %zu bytes < %zu needed",
+                                           arena_bytes, L.total);
+    c->arena = (char*)d_arena;
+  } else {
+    if (hipMalloc((void**)&c->arena, L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      c->arena = nullptr;
+      return fail(c, SD_ENOMEM, "hipMalloc of %zu bytes failed", L.total);
+    }
+    c->own_arena = true;
+  }
+  char* A = c->arena;
+  c->row = (uint32_t*)(A + L.off_row);
+  c->cursor = (uint32_t*)(A + L.off_cursor);
+  c->tile_sums = (uint32_t*)(A + L.off_tiles);
+  c->syn_tgt = A + L.off_tgt;
+  c->syn_dly = (uint8_t*)(A + L.off_dly);
+  c->syn_w = A + L.off_w;
+  c->V = (float*)(A + L.off_V);
+  c->y1 = (float*)(A + L.off_y1);
+  c->y2 = (float*)(A + L.off_y2);
+  c->r = (int32_t*)(A + L.off_r);
+  c->rb = (float*)(A + L.off_rb);
+  c->list[0] = (uint32_t*)(A + L.off_list0);
+  c->list[1] = (uint32_t*)(A + L.off_list1);
+  c->list_cnt[0] = (int32_t*)(A + L.off_cnt0);
+  c->list_cnt[1] = (int32_t*)(A + L.off_cnt1);
+  c->rec = (uint2*)(A + L.off_rec);
+  c->wtab_e = A + L.off_wte;
+  c->wtab_i = A + L.off_wti;
+  c->thr = (uint32_t*)(A + L.off_thr);
+  c->prop64 = (double*)(A + L.off_p64);
+  c->prop32 = (float*)(A + L.off_p32);
+  c->counters = (unsigned long long*)(A + L.off_counters);
+  c->overflow = (int32_t*)(A + L.off_overflow);
+
+  // tables (host, FP64 -> FP32 / BF16 codes)
+  const sd_config& g = *cfg;
+  c->we_h.assign(65536, 0.f);
+  c->wi_h.assign(65536, 0.f);
+  quantile_weights(g, c->we_h.data(), c->wi_h.data());
+  c->mu_e = (float)g.w_exc;
+  c->mu_i = (float)(-g.g * g.w_exc);
+  c->n_thr = poisson_table(g.drive_rate_hz * g.h * 1e-3, c->thr_h, kMaxThr);
+  c->ref_steps = (int32_t)std::llround(g.t_ref / g.h);
+  std::vector<uint32_t> enc_e(65536), enc_i(65536);
+  for (int i = 0; i < 65536; ++i) {
+    if (g.wform == SD_W_FP32) {
+      std::memcpy(&enc_e[i], &c->we_h[i], 4);
+      std::memcpy(&enc_i[i], &c->wi_h[i], 4);
+    } else if (g.wform == SD_W_BF16) {
+      enc_e[i] = bf16_bits_rne(c->we_h[i]);
+      enc_i[i] = bf16_bits_rne(c->wi_h[i]);
+    } else {
+      enc_e[i] = resid_bits(c->we_h[i], c->mu_e);
+      enc_i[i] = resid_bits(c->wi_h[i], c->mu_i);
+    }
+  }
+  if (g.wform == SD_W_FP32) {
+    HIP_TRY(c, hipMemcpyAsync(c->wtab_e, enc_e.data(), 65536 * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->wtab_i, enc_i.data(), 65536 * 4, hipMemcpyHostToDevice, c->stream));
+  } else {
+    std::vector<uint16_t> h_e(65536), h_i(65536);
+    for (int i = 0; i < 65536; ++i) {
+      h_e[i] = (uint16_t)enc_e[i];
+      h_i[i] = (uint16_t)enc_i[i];
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->wtab_e, h_e.data(), 65536 * 2, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->wtab_i, h_i.data(), 65536 * 2, hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->thr, c->thr_h, sizeof(uint32_t) * kMaxThr, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->counters, 0, 8 * 8, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->overflow, 0, 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->list_cnt[0], 0, (size_t)c->NB * 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->list_cnt[1], 0, (size_t)c->NB * 4, c->stream));
+  HIP_TRY(c, launch_propagators(c->stream, g.model, g.h, g.tau_m, g.tau_syn, g.c_m, g.i_e,
+                                c->prop64, c->prop32));
+  HIP_TRY(c, launch_init_state(c->stream, c->N, g.seed, g.v0_lo, g.v0_hi, c->V, c->y1, c->y2,
+                               c->r));
+  HIP_TRY(c, slice_set_lds_limit(160 * 1024));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SD_OK;
+}
+
+void sd_destroy(sd_ctx* c) {
+  if (!c) return;
+  if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
+  if (c->own_arena && c->arena) (void)hipFree(c->arena);
+  if (c->in_list) (void)hipFree(c->in_list);
+  if (c->in_off) (void)hipFree(c->in_off);
+  if (c->in_cnt) (void)hipFree(c->in_cnt);
+  delete c;
+}
+
+const char* sd_last_error(const sd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sd_status sd_build_connections(sd_ctx* c) {
+  if (!c || !c->arena) return SD_EINVAL;
+  const sd_config& g = c->cfg;
+  BuildArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.N = c->N;
+  a.n_src = c->n_src;
+  a.NB = c->NB;
+  a.B = c->B;
+  a.K = c->K;
+  a.k_exc = g.k_exc;
+  if (open_loop(g)) {
+    a.src_e_n = g.n_src_exc;
+    a.src_i_n = g.n_src_inh;
+    a.src_i_base = g.n_src_exc;
+  } else {
+    a.src_e_n = g.n_exc;
+    a.src_i_n = g.n_inh;
+    a.src_i_base = g.n_exc;
+  }
+  a.d_lo = g.d_lo;
+  a.n_dly = g.d_hi - g.d_lo + 1;
+  a.seed = g.seed;
+  a.row = c->row;
+  a.cursor = c->cursor;
+  a.syn_tgt = c->syn_tgt;
+  a.syn_dly = c->syn_dly;
+  a.syn_w = c->syn_w;
+  a.wform = g.wform;
+  a.wtab_e = c->wtab_e;
+  a.wtab_i = c->wtab_i;
+  a.fixed = g.w_cv == 0.0;
+  const float fe = (float)g.w_exc, fi = (float)(-g.g * g.w_exc);
+  a.w_fix_e = fe;
+  a.w_fix_i = fi;
+  if (g.wform == SD_W_BF16) {
+    a.fix_bits_e = bf16_bits_rne(fe);
+    a.fix_bits_i = bf16_bits_rne(fi);
+  } else if (g.wform == SD_W_BF16_RESID) {
+    a.fix_bits_e = resid_bits(fe, c->mu_e);
+    a.fix_bits_i = resid_bits(fi, c->mu_i);
+  }
+  HIP_TRY(c, hipMemsetAsync(c->row, 0, (size_t)c->M * 4, c->stream));
+  if (c->K > 0) HIP_TRY(c, launch_count(c->stream, a));
+  HIP_TRY(c, launch_scan(c->stream, c->row, c->M, c->tile_sums, c->n_tiles));
+  HIP_TRY(c, hipMemcpyAsync(c->cursor, c->row, (size_t)c->M * 4, hipMemcpyDeviceToDevice,
+                            c->stream));
+  if (c->K > 0) HIP_TRY(c, launch_fill(c->stream, a));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint32_t total = 0;
+  HIP_TRY(c, hipMemcpy(&total, c->row + c->M - 1, 4, hipMemcpyDeviceToHost));
+  if ((int64_t)total != c->n_syn)
+    return fail(c, SD_EHIP, "segment table holds %u synapses, expected %lld", total,
+                (long long)c->n_syn);
+  c->built = true;
+  return SD_OK;
+}
+
+sd_status sd_set_count_mode(sd_ctx* c, int32_t on) {
+  if (!c) return SD_EINVAL;
+  c->count_mode = on ? 1 : 0;
+  return SD_OK;
+}
+
+int64_t sd_t_now(const sd_ctx* c) { return c ? c->t_now : -1; }
+
+sd_status sd_get_sizes(const sd_ctx* c, sd_sizes* out) {
+  if (!c || !out) return SD_EINVAL;
+  *out = c->sz;
+  return SD_OK;
+}
+
+sd_status sd_update_neurons(sd_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 1) return fail(c, SD_EINVAL, "n_steps must be >= 1");
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  const int32_t Dmin = c->cfg.d_min;
+  const int64_t in_slice = c->t_now % Dmin;
+  if (in_slice + n_steps > Dmin)
+    return fail(c, SD_EINVAL, "steps [%lld, %lld) cross a slice boundary", (long long)c->t_now,
+                (long long)(c->t_now + n_steps));
+  const bool fresh = in_slice == 0;
+  if (fresh && c->pend_open)
+    return fail(c, SD_ESTATE, "the completed slice at step %lld has not been delivered",
+                (long long)c->pend_t0);
+  SliceArgs a = base_args(c);
+  if (fresh) {
+    c->cur ^= 1;
+    c->pend_t0 = c->t_now;
+  }
+  a.do_deliver = 0;
+  a.n_upd = n_steps;
+  a.t_upd = c->t_now;
+  a.t_slice0 = c->pend_t0;
+  a.out_list = c->list[c->cur];
+  a.out_cnt = c->list_cnt[c->cur];
+  a.append = fresh ? 0 : 1;
+  sd_status s = launch_slice_checked(c, a);
+  if (s != SD_OK) return s;
+  c->pend_open = true;
+  c->t_now += n_steps;
+  return SD_OK;
+}
+
+sd_status sd_deliver_spikes(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
+                            int64_t t0) {
+  if (!c) return SD_EINVAL;
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  const sd_config& g = c->cfg;
+  SliceArgs a = base_args(c);
+  a.do_deliver = 1;
+  a.n_upd = 0;
+  a.t_upd = c->t_now;
+  uint32_t* packed = nullptr;
+  int32_t* d_n = nullptr;
+  if (d_src == nullptr) {
+    if (!c->pend_open || c->t_now % g.d_min != 0 || c->t_now != c->pend_t0 + g.d_min)
+      return fail(c, SD_ESTATE, "no completed slice to deliver");
+    t0 = c->pend_t0;
+    sd_status s = set_pending_input(c, a);
+    if (s != SD_OK) return s;
+  } else {
+    if (n < 0 || !d_lag) return fail(c, SD_EINVAL, "bad spike list");
+    if (t0 + g.d_min < c->t_now)
+      return fail(c, SD_EINVAL, "arrivals at step %lld precede t_now %lld",
+                  (long long)(t0 + g.d_min), (long long)c->t_now);
+    if (t0 + g.d_min + g.d_max > c->t_now + g.ring_len)
+      return fail(c, SD_EINVAL, "arrivals beyond the ring (t0 %lld)", (long long)t0);
+    // pack (src << 5 | lag) into a scratch list: reuse the raster-free path
+    if (n > 0) {
+      HIP_TRY(c, hipMalloc((void**)&packed, (size_t)n * 4 + 256));
+      d_n = (int32_t*)((char*)packed + (size_t)n * 4);
+      std::vector<uint32_t> hs((size_t)n);
+      std::vector<uint8_t> hl((size_t)n);
+      HIP_TRY(c, hipMemcpyAsync(hs.data(), d_src, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(hl.data(), d_lag, (size_t)n, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      for (int64_t i = 0; i < n; ++i) {
+        if ((int64_t)hs[i] >= c->n_src || hl[i] >= g.d_min) {
+          (void)hipFree(packed);
+          return fail(c, SD_EINVAL, "entry %lld: src %u / lag %u out of range", (long long)i,
+                      hs[i], (unsigned)hl[i]);
+        }
+        hs[i] = (hs[i] << 5) | hl[i];
+      }
+      const int32_t nn = (int32_t)n;
+      HIP_TRY(c, hipMemcpyAsync(packed, hs.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(d_n, &nn, 4, hipMemcpyHostToDevice, c->stream));
+    }
+    a.n_regions = 1;
+    a.in_list = packed;
+    a.in_cnt = d_n;
+    a.in_cap = 0;
+    if (n == 0) a.do_deliver = 0;
+  }
+  const int64_t w_lo = t0 + g.d_min;
+  sd_status s = fill_gap(c, w_lo);
+  if (s != SD_OK) return s;
+  a.rb_hi = c->rb_hi;
+  a.w_lo = w_lo;
+  if (a.do_deliver) {
+    s = launch_slice_checked(c, a);
+    if (s != SD_OK) return s;
+  } else {
+    // an empty list still defines the window rows as zero
+    HIP_TRY(c, launch_zero_rows(c->stream, c->rb, c->N, g.ring_len,
+                                std::max(c->rb_hi, w_lo), w_lo + g.d_max));
+  }
+  c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
+  if (packed) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(packed));
+  }
+  if (d_src == nullptr) c->pend_open = false;
+  return SD_OK;
+}
+
+sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
+  if (!c || n_steps < 0) return fail(c, SD_EINVAL, "bad step count");
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  const sd_config& g = c->cfg;
+  const int32_t Dmin = g.d_min;
+  int64_t left = n_steps;
+  while (left > 0) {
+    const int64_t in_slice = c->t_now % Dmin;
+    if (in_slice != 0) {
+      // finish the open slice without delivering (its spikes are not due)
+      const int32_t m = (int32_t)std::min<int64_t>(left, Dmin - in_slice);
+      sd_status s = sd_update_neurons(c, m);
+      if (s != SD_OK) return s;
+      left -= m;
+      continue;
+    }
+    const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);
+    SliceArgs a = base_args(c);
+    const bool deliver = c->pend_open;
+    if (deliver) {
+      sd_status s = set_pending_input(c, a);
+      if (s != SD_OK) return s;
+      a.do_deliver = 1;
+      a.w_lo = c->pend_t0 + Dmin;  // == t_now
+    }
+    a.rb_hi = c->rb_hi;
+    a.n_upd = m;
+    a.t_upd = c->t_now;
+    a.t_slice0 = c->t_now;
+    const int nxt = c->cur ^ 1;
+    a.out_list = c->list[nxt];
+    a.out_cnt = c->list_cnt[nxt];
+    a.append = 0;
+    sd_status s = launch_slice_checked(c, a);
+    if (s != SD_OK) return s;
+    if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
+    c->cur = nxt;
+    c->pend_open = true;
+    c->pend_t0 = c->t_now;
+    c->t_now += m;
+    c->slices += 1;
+    left -= m;
+  }
+  return SD_OK;
+}
+
+sd_status sd_simulate(sd_ctx* c, double t_ms) {
+  if (!c || !(t_ms >= 0.0)) return fail(c, SD_EINVAL, "bad duration");
+  return sd_simulate_steps(c, (int64_t)std::llround(t_ms / c->cfg.h));
+}
+
+sd_status sd_prepare_input(sd_ctx* c, int64_t n_steps) {
+  if (!c || n_steps < 0) return SD_EINVAL;
+  const sd_config& g = c->cfg;
+  if (!open_loop(g)) return fail(c, SD_ESTATE, "closed-loop network has no external input");
+  const int32_t Dmin = g.d_min;
+  // the schedule starts at the slice whose spikes are delivered next
+  const int64_t t_start = c->pend_open ? c->pend_t0 : (c->t_now / Dmin) * Dmin;
+  const int64_t t_end = c->t_now + n_steps;
+  const int64_t n_sl = (t_end - t_start + Dmin - 1) / Dmin;
+  const int64_t steps = n_sl * Dmin;
+  if (c->in_list) (void)hipFree(c->in_list);
+  if (c->in_off) (void)hipFree(c->in_off);
+  if (c->in_cnt) (void)hipFree(c->in_cnt);
+  c->in_list = nullptr;
+  c->in_off = nullptr;
+  c->in_cnt = nullptr;
+  const double p = -std::expm1(-g.src_rate_hz * g.h * 1e-3);
+  const uint32_t thr = (uint32_t)std::floor(p * 4294967296.0);
+  HIP_TRY(c, hipMalloc((void**)&c->in_cnt, (size_t)(n_sl + 1) * 4));
+  HIP_TRY(c, hipMalloc((void**)&c->in_off, (size_t)(n_sl + 1) * 8));
+  HIP_TRY(c, hipMemsetAsync(c->in_cnt, 0, (size_t)(n_sl + 1) * 4, c->stream));
+  HIP_TRY(c, launch_input_count(c->stream, g.seed, c->n_src, t_start, (int32_t)steps, Dmin, thr,
+                                c->in_cnt));
+  std::vector<int32_t> cnt((size_t)n_sl + 1);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->in_cnt, (size_t)(n_sl + 1) * 4, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->in_off_h.assign((size_t)n_sl + 1, 0);
+  for (int64_t k = 0; k < n_sl; ++k) c->in_off_h[k + 1] = c->in_off_h[k] + cnt[k];
+  const int64_t total = c->in_off_h[n_sl];
+  HIP_TRY(c, hipMalloc((void**)&c->in_list, (size_t)std::max<int64_t>(total, 1) * 4));
+  HIP_TRY(c, hipMemcpyAsync(c->in_off, c->in_off_h.data(), (size_t)(n_sl + 1) * 8,
+                            hipMemcpyHostToDevice, c->stream));
+  int32_t* cursor = nullptr;
+  HIP_TRY(c, hipMalloc((void**)&cursor, (size_t)(n_sl + 1) * 4));
+  HIP_TRY(c, hipMemsetAsync(cursor, 0, (size_t)(n_sl + 1) * 4, c->stream));
+  HIP_TRY(c, launch_input_fill(c->stream, g.seed, c->n_src, t_start, (int32_t)steps, Dmin, thr,
+                               c->in_off, cursor, c->in_list));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipFree(cursor));
+  c->in_t0 = t_start;
+  c->in_slices = n_sl;
+  return SD_OK;
+}
+
+sd_status sd_get_stats(sd_ctx* c, sd_stats* out) {
+  if (!c || !out) return SD_EINVAL;
+  unsigned long long cnt[4];
+  int32_t ov = 0;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&ov, c->overflow, 4, hipMemcpyDeviceToHost));
+  out->t_now = c->t_now;
+  out->events_delivered = (int64_t)cnt[0];
+  out->spikes_delivered = (int64_t)cnt[1];
+  out->spikes_emitted = (int64_t)cnt[2];
+  out->spikes_recorded = (int64_t)std::min<unsigned long long>(cnt[3], (unsigned long long)c->rec_cap);
+  out->slices = c->slices;
+  out->overflow = ov;
+  return ov ? SD_EOVERFLOW : SD_OK;
+}
+
+sd_status sd_read_ring(sd_ctx* c, float* h_out, int32_t n_slots) {
+  if (!c || !h_out || n_slots < 0 || n_slots > c->cfg.ring_len) return SD_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int32_t L = c->cfg.ring_len;
+  for (int32_t s = 0; s < n_slots; ++s) {
+    const int64_t t = c->t_now + s;
+    float* dst = h_out + (size_t)s * c->N;
+    if (t < c->rb_hi) {
+      HIP_TRY(c, hipMemcpy(dst, c->rb + (t % L) * c->N, (size_t)c->N * 4, hipMemcpyDeviceToHost));
+    } else {
+      std::memset(dst, 0, (size_t)c->N * 4);
+    }
+  }
+  return SD_OK;
+}
+
+sd_status sd_read_state(sd_ctx* c, float* h_v, float* h_y1, float* h_y2, int32_t* h_r) {
+  if (!c) return SD_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t n = (size_t)c->N * 4;
+  if (h_v) HIP_TRY(c, hipMemcpy(h_v, c->V, n, hipMemcpyDeviceToHost));
+  if (h_y1) HIP_TRY(c, hipMemcpy(h_y1, c->y1, n, hipMemcpyDeviceToHost));
+  if (h_y2) HIP_TRY(c, hipMemcpy(h_y2, c->y2, n, hipMemcpyDeviceToHost));
+  if (h_r) HIP_TRY(c, hipMemcpy(h_r, c->r, n, hipMemcpyDeviceToHost));
+  return SD_OK;
+}
+
+sd_status sd_write_state(sd_ctx* c, const float* h_v, const float* h_y1, const float* h_y2,
+                         const int32_t* h_r) {
+  if (!c) return SD_EINVAL;
+  const size_t n = (size_t)c->N * 4;
+  if (h_v) HIP_TRY(c, hipMemcpyAsync(c->V, h_v, n, hipMemcpyHostToDevice, c->stream));
+  if (h_y1) HIP_TRY(c, hipMemcpyAsync(c->y1, h_y1, n, hipMemcpyHostToDevice, c->stream));
+  if (h_y2) HIP_TRY(c, hipMemcpyAsync(c->y2, h_y2, n, hipMemcpyHostToDevice, c->stream));
+  if (h_r) HIP_TRY(c, hipMemcpyAsync(c->r, h_r, n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SD_OK;
+}
+
+sd_status sd_get_spikes(sd_ctx* c, int64_t* h_step, uint32_t* h_id, int64_t cap, int64_t* n) {
+  if (!c || !n) return SD_EINVAL;
+  *n = 0;
+  if (c->rec_cap == 0) return fail(c, SD_ESTATE, "spike recording is off");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long total = 0;
+  HIP_TRY(c, hipMemcpy(&total, c->counters + 3, 8, hipMemcpyDeviceToHost));
+  const int64_t avail = std::min<int64_t>((int64_t)total, c->rec_cap) - c->rec_read;
+  const int64_t m = std::min<int64_t>(avail, cap);
+  if (m > 0) {
+    std::vector<uint2> buf((size_t)m);
+    HIP_TRY(c, hipMemcpy(buf.data(), c->rec + c->rec_read, (size_t)m * 8, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+      if (h_step) h_step[i] = buf[i].x;
+      if (h_id) h_id[i] = buf[i].y;
+    }
+    c->rec_read += m;
+  }
+  *n = std::max<int64_t>(m, 0);
+  return (int64_t)total > c->rec_cap ? SD_EOVERFLOW : SD_OK;
+}
+
+sd_status sd_get_pending(sd_ctx* c, uint32_t* h_src, uint8_t* h_lag, int64_t cap, int64_t* n,
+                         int64_t* slice_t0) {
+  if (!c || !n) return SD_EINVAL;
+  *n = 0;
+  if (slice_t0) *slice_t0 = c->pend_open ? c->pend_t0 : -1;
+  if (!c->pend_open || open_loop(c->cfg)) return SD_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> cnt((size_t)c->NB);
+  HIP_TRY(c, hipMemcpy(cnt.data(), c->list_cnt[c->cur], (size_t)c->NB * 4, hipMemcpyDeviceToHost));
+  std::vector<uint32_t> buf((size_t)c->NB * c->out_cap);
+  HIP_TRY(c, hipMemcpy(buf.data(), c->list[c->cur], buf.size() * 4, hipMemcpyDeviceToHost));
+  // gather, then order by (lag, src)
+  std::vector<uint32_t> all;
+  for (int32_t b = 0; b < c->NB; ++b)
+    for (int32_t i = 0; i < cnt[b]; ++i) all.push_back(buf[(size_t)b * c->out_cap + i]);
+  std::sort(all.begin(), all.end(), [](uint32_t x, uint32_t y) {
+    const uint32_t lx = x & 31u, ly = y & 31u;
+    return lx != ly ? lx < ly : (x >> 5) < (y >> 5);
+  });
+  const int64_t m = std::min<int64_t>((int64_t)all.size(), cap);
+  for (int64_t i = 0; i < m; ++i) {
+    if (h_src) h_src[i] = all[i] >> 5;
+    if (h_lag) h_lag[i] = (uint8_t)(all[i] & 31u);
+  }
+  *n = (int64_t)all.size();
+  return SD_OK;
+}
+
+sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
+                                float* h_w) {
+  if (!c || !h_row) return SD_EINVAL;
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // per-source rows from the (source, block) pointers
+  std::vector<uint32_t> rp((size_t)c->M);
+  HIP_TRY(c, hipMemcpy(rp.data(), c->row, (size_t)c->M * 4, hipMemcpyDeviceToHost));
+  for (int64_t s = 0; s <= c->n_src; ++s) h_row[s] = rp[(size_t)(s * c->NB)];
+  if (!h_tgt && !h_dly && !h_w) return SD_OK;
+  int32_t* d_t = nullptr;
+  float* d_w = nullptr;
+  HIP_TRY(c, hipMalloc((void**)&d_t, (size_t)std::max<int64_t>(c->n_syn, 1) * 4));
+  HIP_TRY(c, hipMalloc((void**)&d_w, (size_t)std::max<int64_t>(c->n_syn, 1) * 4));
+  HIP_TRY(c, launch_decode_export(c->stream, c->syn_tgt, c->syn_w, c->cfg.wform, c->row, 0,
+                                  c->n_src, c->NB, c->B, c->src_e_end, c->mu_e, c->mu_i, d_t, d_w));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h_tgt) HIP_TRY(c, hipMemcpy(h_tgt, d_t, (size_t)c->n_syn * 4, hipMemcpyDeviceToHost));
+  if (h_w) HIP_TRY(c, hipMemcpy(h_w, d_w, (size_t)c->n_syn * 4, hipMemcpyDeviceToHost));
+  if (h_dly) HIP_TRY(c, hipMemcpy(h_dly, c->syn_dly, (size_t)c->n_syn, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipFree(d_t));
+  HIP_TRY(c, hipFree(d_w));
+  return SD_OK;
+}
+
+sd_status sd_export_segments(sd_ctx* c, int64_t src, int64_t* h_ptr) {
+  if (!c || !h_ptr || src < 0 || src >= c->n_src) return SD_EINVAL;
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<uint32_t> rp((size_t)c->NB + 1);
+  HIP_TRY(c, hipMemcpy(rp.data(), c->row + src * c->NB, rp.size() * 4, hipMemcpyDeviceToHost));
+  for (int32_t b = 0; b <= c->NB; ++b) h_ptr[b] = rp[(size_t)b];
+  return SD_OK;
+}
+
+sd_status sd_host_tables(const sd_config* cfg, float* h_we, float* h_wi, uint32_t* h_thr,
+                         int32_t* n_thr) {
+  std::string why;
+  if (check_config(cfg, &why) != SD_OK) return SD_EINVAL;
+  std::vector<float> we(65536), wi(65536);
+  quantile_weights(*cfg, we.data(), wi.data());
+  if (cfg->w_cv == 0.0) {
+    std::fill(we.begin(), we.end(), (float)cfg->w_exc);
+    std::fill(wi.begin(), wi.end(), (float)(-cfg->g * cfg->w_exc));
+  }
+  // decode to the storage form
+  const float mu_e = (float)cfg->w_exc, mu_i = (float)(-cfg->g * cfg->w_exc);
+  for (int i = 0; i < 65536; ++i) {
+    if (cfg->wform == SD_W_BF16) {
+      const uint32_t be = (uint32_t)bf16_bits_rne(we[i]) << 16, bi = (uint32_t)bf16_bits_rne(wi[i]) << 16;
+      std::memcpy(&we[i], &be, 4);
+      std::memcpy(&wi[i], &bi, 4);
+    } else if (cfg->wform == SD_W_BF16_RESID) {
+      const uint32_t de = (uint32_t)resid_bits(we[i], mu_e) << 16, di = (uint32_t)resid_bits(wi[i], mu_i) << 16;
+      float fe, fi;
+      std::memcpy(&fe, &de, 4);
+      std::memcpy(&fi, &di, 4);
+      we[i] = (float)((double)mu_e + (double)mu_e * (double)fe);
+      wi[i] = (float)((double)mu_i + (double)mu_i * (double)fi);
+    }
+  }
+  if (h_we) std::memcpy(h_we, we.data(), 65536 * 4);
+  if (h_wi) std::memcpy(h_wi, wi.data(), 65536 * 4);
+  uint32_t thr[kMaxThr];
+  const int n = poisson_table(cfg->drive_rate_hz * cfg->h * 1e-3, thr, kMaxThr);
+  if (h_thr) std::memcpy(h_thr, thr, sizeof thr);
+  if (n_thr) *n_thr = n;
+  return SD_OK;
+}
+
+sd_status sd_export_block(sd_ctx* c, int32_t b, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
+                          float* h_w, int64_t* n_out) {
+  if (!c || !h_row || b < 0 || b >= c->NB) return SD_EINVAL;
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // pointers of column b: row[s * NB + b], row[s * NB + b + 1]
+  std::vector<uint32_t> rp((size_t)c->M);
+  HIP_TRY(c, hipMemcpy(rp.data(), c->row, (size_t)c->M * 4, hipMemcpyDeviceToHost));
+  std::vector<uint32_t> lo((size_t)c->n_src), len((size_t)c->n_src);
+  int64_t tot = 0;
+  h_row[0] = 0;
+  for (int64_t s = 0; s < c->n_src; ++s) {
+    lo[s] = rp[(size_t)(s * c->NB + b)];
+    len[s] = rp[(size_t)(s * c->NB + b + 1)] - lo[s];
+    tot += len[s];
+    h_row[s + 1] = tot;
+  }
+  if (n_out) *n_out = tot;
+  if (!h_tgt) return SD_OK;
+  const int bt = c->cfg.wform == SD_W_FP32 ? 4 : 2;
+  for (int64_t s = 0; s < c->n_src; ++s) {
+    if (!len[s]) continue;
+    const int64_t at = h_row[s];
+    std::vector<uint8_t> tb((size_t)len[s] * bt), wb((size_t)len[s] * bt);
+    HIP_TRY(c, hipMemcpy(tb.data(), (char*)c->syn_tgt + (size_t)lo[s] * bt, tb.size(),
+                         hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(wb.data(), (char*)c->syn_w + (size_t)lo[s] * bt, wb.size(),
+                         hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(h_dly + at, c->syn_dly + lo[s], (size_t)len[s], hipMemcpyDeviceToHost));
+    const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
+    for (uint32_t i = 0; i < len[s]; ++i) {
+      if (bt == 4) {
+        std::memcpy(&h_tgt[at + i], &tb[(size_t)i * 4], 4);
+        std::memcpy(&h_w[at + i], &wb[(size_t)i * 4], 4);
+      } else {
+        uint16_t o, wbits;
+        std::memcpy(&o, &tb[(size_t)i * 2], 2);
+        std::memcpy(&wbits, &wb[(size_t)i * 2], 2);
+        h_tgt[at + i] = (int32_t)((int64_t)b * c->B + o);
+        const uint32_t u = (uint32_t)wbits << 16;
+        float d;
+        std::memcpy(&d, &u, 4);
+        h_w[at + i] = c->cfg.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
+      }
+    }
+  }
+  return SD_OK;
+}
+
+sd_status sd_get_tables(sd_ctx* c, float* h_we, float* h_wi, uint32_t* h_thr, int32_t* n_thr,
+                        double* h_prop, float* h_prop32) {
+  if (!c) return SD_EINVAL;
+  if (h_we) std::memcpy(h_we, c->we_h.data(), 65536 * 4);
+  if (h_wi) std::memcpy(h_wi, c->wi_h.data(), 65536 * 4);
+  if (h_thr) std::memcpy(h_thr, c->thr_h, sizeof(uint32_t) * kMaxThr);
+  if (n_thr) *n_thr = c->n_thr;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h_prop) HIP_TRY(c, hipMemcpy(h_prop, c->prop64, 7 * 8, hipMemcpyDeviceToHost));
+  if (h_prop32) HIP_TRY(c, hipMemcpy(h_prop32, c->prop32, 8 * 4, hipMemcpyDeviceToHost));
+  return SD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// sd_internal.h -- shared declarations between the host library and the
+// gfx950 kernels (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sd {
+
+enum { STREAM_SYN = 1, STREAM_INIT = 2, STREAM_DRIVE = 3, STREAM_SRC = 4 };
+enum { MODEL_DELTA = 0, MODEL_ALPHA = 1 };
+enum { WF_FP32 = 0, WF_BF16 = 1, WF_BF16_RESID = 2 };
+
+constexpr int kMaxThr = 64;        // Poisson-drive threshold table entries
+constexpr int kSliceThreads = 1024;  // threads of a slice workgroup
+constexpr int kFillThreads = 512;    // threads of a build workgroup
+constexpr int kFillChunk = 2048;     // draws ranked per build iteration
+
+// Everything a slice launch needs (passed by value).
+struct SliceArgs {
+  // network layout
+  const uint32_t* row;     // [n_src * NB + 1] segment pointers, source-major
+  const void* syn_tgt;     // i32 target id (FP32 form) or u16 offset in block
+  const uint8_t* syn_dly;  // u8 delay in steps
+  const void* syn_w;       // f32 weight, bf16 weight or bf16 residual
+  int64_t N;               // local neurons
+  int32_t NB, B;           // blocks, neurons per block
+  int32_t Dmin, Dmax, L;
+  int64_t src_e_end;       // source ids below this are excitatory
+  float mu_e, mu_i;        // population means of the residual form
+  int32_t count_mode;      // deliver 1.0 per synapse
+  int32_t grid_per_xcd;    // blocks handled by one XCD (ceil(NB / 8))
+  // delivery
+  int32_t do_deliver;
+  int32_t n_regions;       // spike-list regions to read
+  const uint32_t* in_list; // region r at in_list + r * in_cap
+  const int32_t* in_cnt;   // entries per region (device)
+  int32_t in_cap;
+  int64_t w_lo;            // first step of the delivery window
+  // update
+  int32_t n_upd;           // steps to update (0: none)
+  int64_t t_upd;           // first step to update
+  int64_t t_slice0;        // start step of the slice the new spikes belong to
+  float* V;
+  float* y1;
+  float* y2;
+  int32_t* r;
+  const float* prop;       // P11 P21 P22 P31 P32 P33 P30*I_e in_scale (FP32)
+  const uint32_t* thr;     // Poisson-drive thresholds
+  int32_t n_thr;
+  uint64_t seed;
+  float e_l, v_th, v_reset, drive_w;
+  int32_t ref_steps;
+  int32_t model;
+  // ring buffer [L][N]
+  float* rb;
+  int64_t rb_hi;           // rows of steps in [., rb_hi) hold valid sums
+  // new spikes
+  int32_t write_list;      // closed loop: feed spikes back
+  uint32_t* out_list;      // region b at out_list + b * out_cap
+  int32_t* out_cnt;
+  int32_t out_cap;
+  int32_t append;          // continue the region's existing entries
+  uint2* rec;              // raster (step, id); null: off
+  unsigned long long* rec_n;
+  int64_t rec_cap;
+  // counters
+  unsigned long long* ev_count;    // synaptic events delivered
+  unsigned long long* spk_in_count;// spike entries delivered
+  unsigned long long* spk_count;   // spikes emitted
+  int32_t* overflow;               // bit 0: list, bit 1: raster, bit 2: bad entry
+};
+
+struct BuildArgs {
+  int64_t N, n_src;
+  int32_t NB, B, K, k_exc;
+  int64_t src_e_n, src_i_n, src_i_base;
+  int32_t d_lo, n_dly;
+  uint64_t seed;
+  uint32_t* row;           // counts, then exclusive scan
+  uint32_t* cursor;        // fill cursors (copy of row)
+  void* syn_tgt;
+  uint8_t* syn_dly;
+  void* syn_w;
+  int32_t wform;
+  const void* wtab_e;      // encoded weight per quantile index (f32 or bf16 bits)
+  const void* wtab_i;
+  float w_fix_e, w_fix_i;  // fixed weights (cv == 0), encoded at use
+  uint32_t fix_bits_e, fix_bits_i;
+  int32_t fixed;
+};
+
+// launch wrappers (sd_kernels.hip)
+hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,
+                              double c_m, double i_e, double* prop64, float* prop32);
+hipError_t launch_init_state(hipStream_t s, int64_t N, uint64_t seed, double v0_lo, double v0_hi,
+                             float* V, float* y1, float* y2, int32_t* r);
+hipError_t launch_count(hipStream_t s, const BuildArgs& a);
+hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_sums,
+                       int64_t n_tiles_cap);
+hipError_t launch_fill(hipStream_t s, const BuildArgs& a);
+hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform);
+size_t slice_lds_bytes(int B, int Dmin, int Dmax, int n_regions);
+hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
+                            int64_t t_hi);
+hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
+                              int32_t n_steps, int32_t Dmin, uint32_t thr, int32_t* cnt);
+hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
+                             int32_t n_steps, int32_t Dmin, uint32_t thr, const int64_t* off,
+                             int32_t* cursor, uint32_t* list);
+hipError_t launch_decode_export(hipStream_t s, const void* syn_tgt, const void* syn_w, int wform,
+                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
+                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
+                                int32_t* tgt_out, float* w_out);
+hipError_t slice_set_lds_limit(size_t bytes);
+
+}  // namespace sd

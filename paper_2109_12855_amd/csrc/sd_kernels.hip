@@ -1,0 +1,788 @@
+// sd_kernels.hip -- gfx950 kernels of the spike-delivery library.
+//
+// Hot path (one fused launch per slice of d_min steps):
+//   k_slice: a workgroup owns one block of B target neurons.  It first walks
+//   the target segments of every spike of the completed slice (Alg. REF,
+//   Sec. 3.2) and adds each weight into an LDS copy of its block's ring
+//   window (d_max rows x B neurons), then advances its neurons through the
+//   next slice with the exact propagators (Sec. 2.1), reading inputs straight
+//   from the LDS window, and finally compacts the new spikes with a bitmask +
+//   block scan into the block's list, ordered (lag, neuron).  Rows of the
+//   window that are due in later slices are written to the ring in HBM.
+//
+// Build (once, untimed, Sec. 2.2):
+//   k_count / scan / k_fill lay out the source-major, block-partitioned
+//   table: segment (src, b) holds the synapses from src into block b in
+//   (target, draw) order.  k_fill ranks equal sources inside each chunk of
+//   draws with an LDS bitonic sort, so the layout is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "sd_internal.h"
+
+namespace sd {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11); counter (c0, c1, 0, 0), key (seed,
+// stream).  Device-only implementation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1,
+                                       uint64_t out[4]) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, k0 = seed, k1 = stream;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t hi0 = __umul64hi(M0, x0), lo0 = M0 * x0;
+    const uint64_t hi1 = __umul64hi(M1, x2), lo1 = M1 * x2;
+    const uint64_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
+    x0 = n0;
+    x1 = lo1;
+    x2 = n2;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// floor(r * n / 2^64)
+__device__ __forceinline__ uint64_t mul_range(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// The once-per-run FP64 work: exact propagators of the linear subthreshold
+// dynamics over one step, then their FP32 roundings for the update.
+__global__ void k_propagators(int model, double h, double tau_m, double tau_syn, double c_m,
+                              double i_e, double* p64, float* p32) {
+  const double em = exp(-h / tau_m);
+  double P11 = 0.0, P21 = 0.0, P22 = 0.0, P31 = 0.0, P32 = 0.0;
+  const double P33 = em;
+  const double P30 = -(tau_m / c_m) * expm1(-h / tau_m);
+  double in_scale = 1.0;
+  if (model == MODEL_ALPHA) {
+    const double es = exp(-h / tau_syn);
+    const double a = 1.0 / tau_syn - 1.0 / tau_m;  // rate difference
+    const double x = a * h;
+    P11 = es;
+    P22 = es;
+    P21 = h * es;
+    P32 = (em - es) / (a * c_m);
+    P31 = em * (-expm1(-x) - x * exp(-x)) / (a * a * c_m);
+    in_scale = exp(1.0) / tau_syn;
+  }
+  const double v[7] = {P11, P21, P22, P31, P32, P33, P30};
+  for (int i = 0; i < 7; ++i) p64[i] = v[i];
+  for (int i = 0; i < 6; ++i) p32[i] = (float)v[i];
+  p32[6] = (float)(P30 * i_e);
+  p32[7] = (float)in_scale;
+}
+
+__global__ void k_init_state(int64_t N, uint64_t seed, double v0_lo, double v0_hi, float* V,
+                             float* y1, float* y2, int32_t* r) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  uint64_t w[4];
+  philox(seed, STREAM_INIT, (uint64_t)j, 0, w);
+  const double u = (double)(w[0] >> 11) * 0x1.0p-53;
+  V[j] = (float)__dadd_rn(v0_lo, __dmul_rn(v0_hi - v0_lo, u));
+  y1[j] = 0.f;
+  y2[j] = 0.f;
+  r[j] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// connection build
+// ---------------------------------------------------------------------------
+struct Draw {
+  uint32_t src;
+  uint32_t dly;
+  uint32_t widx;
+  uint32_t inh;
+};
+
+__device__ __forceinline__ Draw draw_synapse(const BuildArgs& a, int64_t j, int32_t k) {
+  uint64_t w[4];
+  philox(a.seed, STREAM_SYN, (uint64_t)j, (uint64_t)k, w);
+  Draw d;
+  d.inh = k >= a.k_exc;
+  d.src = d.inh ? (uint32_t)(a.src_i_base + (int64_t)mul_range(w[0], (uint64_t)a.src_i_n))
+                : (uint32_t)mul_range(w[0], (uint64_t)a.src_e_n);
+  d.dly = (uint32_t)(a.d_lo + (int32_t)mul_range(w[1], (uint64_t)a.n_dly));
+  d.widx = (uint32_t)(w[2] >> 48);
+  return d;
+}
+
+// histogram of (source, block) pairs; one workgroup per target
+__global__ void __launch_bounds__(256) k_count(BuildArgs a) {
+  const int64_t j = blockIdx.x;
+  const int32_t b = (int32_t)(j / a.B);
+  for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
+    const Draw d = draw_synapse(a, j, k);
+    atomicAdd(&a.row[(int64_t)d.src * a.NB + b], 1u);
+  }
+}
+
+// three-phase exclusive scan of a u32 array (tiles of 4096)
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// exclusive block scan of one value per thread; sh holds nthreads/64 + 1 words
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* sh, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = 0;
+    for (int i = 0; i < nw; ++i) {
+      const T x = sh[i];
+      sh[i] = acc;
+      acc += x;
+    }
+    sh[nw] = acc;
+  }
+  __syncthreads();
+  const T res = inc - v + sh[w];
+  total = sh[nw];
+  __syncthreads();
+  return res;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* data, int64_t n,
+                                                            uint32_t* tile_sums) {
+  __shared__ uint32_t sh[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i)
+    if (base + i < n) s += data[base + i];
+  uint32_t tot;
+  block_excl_scan<uint32_t>(s, sh, tot);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* tile_sums, int64_t n_tiles) {
+  __shared__ uint32_t sh[kScanThreads / 64 + 1];
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n_tiles; c0 += kScanThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const uint32_t v = i < n_tiles ? tile_sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(v, sh, tot);
+    if (i < n_tiles) tile_sums[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(uint32_t* data, int64_t n,
+                                                            const uint32_t* tile_sums) {
+  __shared__ uint32_t sh[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = (base + i < n) ? data[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<uint32_t>(s, sh, tot) + tile_sums[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (base + i < n) data[base + i] = run;
+    run += v[i];
+  }
+}
+
+// Deterministic fill: workgroup b walks the draws of its block in
+// (target, k) order, kFillChunk at a time; equal sources inside a chunk are
+// ranked by an LDS bitonic sort of (src, position) keys, so each segment
+// receives its synapses in draw order.  Only workgroup b touches the cursors
+// of column b.
+__global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
+  __shared__ uint64_t keys[kFillChunk];
+  __shared__ uint32_t meta[kFillChunk];  // widx | inh << 16 | dly << 24
+  const int32_t b = blockIdx.x;
+  const int64_t j0 = (int64_t)b * a.B;
+  const int64_t nb = (a.N - j0) < a.B ? (a.N - j0) : a.B;
+  const int64_t n_el = nb * a.K;
+  const int tid = threadIdx.x;
+  for (int64_t c0 = 0; c0 < n_el; c0 += kFillChunk) {
+    const int n_in = (int)((n_el - c0) < kFillChunk ? (n_el - c0) : kFillChunk);
+    for (int i = tid; i < kFillChunk; i += kFillThreads) {
+      if (i < n_in) {
+        const int64_t e = c0 + i;
+        const int64_t jl = e / a.K;
+        const int32_t k = (int32_t)(e - jl * a.K);
+        const Draw d = draw_synapse(a, j0 + jl, k);
+        keys[i] = ((uint64_t)d.src << 11) | (uint64_t)i;
+        meta[i] = d.widx | (d.inh << 16) | (d.dly << 24);
+      } else {
+        keys[i] = ~0ULL;
+      }
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= kFillChunk; kk <<= 1) {
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int i = tid; i < kFillChunk; i += kFillThreads) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const uint64_t x = keys[i], y = keys[ixj];
+            const bool up = (i & kk) == 0;
+            if ((x > y) == up) {
+              keys[i] = y;
+              keys[ixj] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int p = tid; p < n_in; p += kFillThreads) {
+      const uint64_t key = keys[p];
+      const uint32_t src = (uint32_t)(key >> 11);
+      const int idx = (int)(key & 2047);
+      int rank = 0;
+      while (p - rank - 1 >= 0 && (uint32_t)(keys[p - rank - 1] >> 11) == src) ++rank;
+      const int64_t cell = (int64_t)src * a.NB + b;
+      const int64_t pos = (int64_t)a.cursor[cell] + rank;
+      const uint32_t m = meta[idx];
+      const uint32_t widx = m & 0xffffu, inh = (m >> 16) & 1u, dly = m >> 24;
+      const int64_t jl = (c0 + idx) / a.K;
+      a.syn_dly[pos] = (uint8_t)dly;
+      if (a.wform == WF_FP32) {
+        ((int32_t*)a.syn_tgt)[pos] = (int32_t)(j0 + jl);
+        float w;
+        if (a.fixed) w = inh ? a.w_fix_i : a.w_fix_e;
+        else w = inh ? ((const float*)a.wtab_i)[widx] : ((const float*)a.wtab_e)[widx];
+        ((float*)a.syn_w)[pos] = w;
+      } else {
+        ((uint16_t*)a.syn_tgt)[pos] = (uint16_t)jl;
+        uint16_t wb;
+        if (a.fixed) wb = (uint16_t)(inh ? a.fix_bits_i : a.fix_bits_e);
+        else wb = inh ? ((const uint16_t*)a.wtab_i)[widx] : ((const uint16_t*)a.wtab_e)[widx];
+        ((uint16_t*)a.syn_w)[pos] = wb;
+      }
+    }
+    __syncthreads();
+    for (int p = tid; p < n_in; p += kFillThreads) {
+      const uint32_t src = (uint32_t)(keys[p] >> 11);
+      const bool last = (p == n_in - 1) || ((uint32_t)(keys[p + 1] >> 11) != src);
+      if (last) {
+        int run = 1;
+        while (p - run >= 0 && (uint32_t)(keys[p - run] >> 11) == src) ++run;
+        a.cursor[(int64_t)src * a.NB + b] += (uint32_t)run;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused slice kernel
+// ---------------------------------------------------------------------------
+template <int WF>
+__device__ __forceinline__ float syn_weight(const void* w, int64_t e, float mu) {
+  if constexpr (WF == WF_FP32) {
+    return ((const float*)w)[e];
+  } else if constexpr (WF == WF_BF16) {
+    return __uint_as_float((uint32_t)((const uint16_t*)w)[e] << 16);
+  } else {
+    const float d = __uint_as_float((uint32_t)((const uint16_t*)w)[e] << 16);
+    return fmaf(mu, d, mu);
+  }
+}
+
+template <int WF>
+__device__ __forceinline__ int syn_offset(const void* t, int64_t e, int32_t j0) {
+  if constexpr (WF == WF_FP32) return ((const int32_t*)t)[e] - j0;
+  else return (int)((const uint16_t*)t)[e];
+}
+
+__device__ __forceinline__ int rl_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ float rl_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+size_t slice_lds_bytes(int B, int Dmin, int Dmax, int n_regions) {
+  return (size_t)Dmax * B * 4 + (size_t)Dmin * (B / 32) * 4 + (size_t)(n_regions + 1) * 4 +
+         (size_t)(kSliceThreads / 64 + 1) * 4 + 16;
+}
+
+constexpr int kUnroll = 8;
+
+template <int WF>
+__global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int gx = blockIdx.x;
+  // XCD-aware mapping: consecutive blocks run on the same XCD so they share
+  // segment-pointer lines and segment boundaries in that XCD's L2.
+  const int b = (gx & 7) * a.grid_per_xcd + (gx >> 3);
+  if (b >= a.NB) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  constexpr int nwv = kSliceThreads / 64;
+  const int B = a.B;
+  const int64_t j0 = (int64_t)b * B;
+  const int nb = (int)((a.N - j0) < B ? (a.N - j0) : B);
+  const int Wd = B >> 5;
+
+  float* win = (float*)lds_raw;
+  uint32_t* mask = (uint32_t*)(win + (size_t)a.Dmax * B);
+  int32_t* pre = (int32_t*)(mask + (size_t)a.Dmin * Wd);
+  int32_t* scr = pre + a.n_regions + 1;
+
+  if (a.do_deliver) {
+    for (int i = tid; i < a.Dmax * B; i += kSliceThreads) win[i] = 0.f;
+  }
+  for (int i = tid; i < a.Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
+
+  // ---- deliver the completed slice into the LDS window (Alg. REF) -------
+  if (a.do_deliver) {
+    // prefix of region counts
+    const int R = a.n_regions;
+    const int per = (R + kSliceThreads - 1) / kSliceThreads;
+    int s = 0;
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) s += a.in_cnt[r];
+    }
+    int tot;
+    int ex = block_excl_scan<int>(s, scr, tot);
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) {
+        pre[r] = ex;
+        ex += a.in_cnt[r];
+      }
+    }
+    if (tid == 0) pre[R] = tot;
+    __syncthreads();
+    const int64_t total = tot;
+
+    uint64_t ev = 0;
+    const int Dmin = a.Dmin;
+    for (int64_t base = (int64_t)wv * 64; base < total; base += (int64_t)nwv * 64) {
+      const int64_t i = base + lane;
+      uint32_t lo = 0;
+      int len = 0, lag = 0;
+      float mu = 0.f;
+      if (i < total) {
+        int rlo = 0, rhi = R;
+        while (rhi - rlo > 1) {
+          const int m = (rlo + rhi) >> 1;
+          if (pre[m] <= i) rlo = m;
+          else rhi = m;
+        }
+        const uint32_t ent = a.in_list[(int64_t)rlo * a.in_cap + (i - pre[rlo])];
+        const uint32_t src = ent >> 5;
+        lag = (int)(ent & 31u);
+        if (lag < Dmin) {
+          const int64_t p = (int64_t)src * a.NB + b;
+          lo = a.row[p];
+          len = (int)(a.row[p + 1] - lo);
+          mu = ((int64_t)src < a.src_e_end) ? a.mu_e : a.mu_i;
+        } else {
+          atomicOr(a.overflow, 4);
+        }
+      }
+      ev += (uint64_t)len;
+      const int n_here = (int)((total - base) < 64 ? (total - base) : 64);
+      for (int s0 = 0; s0 < n_here; s0 += kUnroll) {
+        uint32_t slo[kUnroll];
+        int slen[kUnroll], sslot[kUnroll];
+        float smu[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          slo[u] = (uint32_t)rl_i((int)lo, s0 + u);
+          slen[u] = rl_i(len, s0 + u);
+          sslot[u] = rl_i(lag, s0 + u) - Dmin;
+          smu[u] = rl_f(mu, s0 + u);
+        }
+        int off[kUnroll], dl[kUnroll];
+        float w[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (lane < slen[u]) {
+            const int64_t e = (int64_t)slo[u] + lane;
+            off[u] = syn_offset<WF>(a.syn_tgt, e, (int32_t)j0);
+            dl[u] = a.syn_dly[e];
+            w[u] = syn_weight<WF>(a.syn_w, e, smu[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (lane < slen[u]) {
+            const float v = a.count_mode ? 1.f : w[u];
+            __hip_atomic_fetch_add(&win[(sslot[u] + dl[u]) * B + off[u]], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+        // segments longer than one wave
+        for (int u = 0; u < kUnroll; ++u) {
+          for (int e0 = 64; e0 < slen[u]; e0 += 64) {
+            if (lane + e0 < slen[u]) {
+              const int64_t e = (int64_t)slo[u] + e0 + lane;
+              const int o = syn_offset<WF>(a.syn_tgt, e, (int32_t)j0);
+              const int d = a.syn_dly[e];
+              const float v = a.count_mode ? 1.f : syn_weight<WF>(a.syn_w, e, smu[u]);
+              __hip_atomic_fetch_add(&win[(sslot[u] + d) * B + o], v, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+      }
+    }
+    // events of this wave
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
+    if (lane == 0 && ev) atomicAdd(a.ev_count, (unsigned long long)ev);
+    if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+  }
+  __syncthreads();
+
+  // ---- update the next slice's steps (exact propagation, Sec. 2.1) -------
+  if (a.n_upd > 0) {
+    const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
+    const float P32 = a.prop[4], P33 = a.prop[5], P30Ie = a.prop[6], insc = a.prop[7];
+    const int L = a.L;
+    for (int n = tid; n < nb; n += kSliceThreads) {
+      const int64_t gn = j0 + n;
+      float V = a.V[gn];
+      int r = a.r[gn];
+      float y1 = 0.f, y2 = 0.f;
+      if (a.model == MODEL_ALPHA) {
+        y1 = a.y1[gn];
+        y2 = a.y2[gn];
+      }
+      uint64_t rr[4] = {0, 0, 0, 0};
+      int64_t chunk = -1;
+      for (int s = 0; s < a.n_upd; ++s) {
+        const int64_t t = a.t_upd + s;
+        float in = 0.f;
+        if (t < a.rb_hi) in = a.rb[(t % L) * a.N + gn];
+        if (a.do_deliver) {
+          const int64_t q = t - a.w_lo;
+          if (q >= 0 && q < a.Dmax) in += win[q * B + n];
+        }
+        if ((t >> 3) != chunk) {
+          chunk = t >> 3;
+          philox(a.seed, STREAM_DRIVE, (uint64_t)gn, (uint64_t)chunk, rr);
+        }
+        const uint64_t word = rr[(t & 7) >> 1];
+        const uint32_t u = (t & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+        int c = 0;
+        for (int k = 0; k < a.n_thr; ++k) c += (u >= a.thr[k]) ? 1 : 0;
+        const float drive = (float)c * a.drive_w;
+        if (a.model == MODEL_DELTA) {
+          if (r > 0) --r;
+          else V = a.e_l + P33 * (V - a.e_l) + P30Ie + in + drive;
+        } else {
+          if (r == 0) V = a.e_l + P31 * y1 + P32 * y2 + P33 * (V - a.e_l) + P30Ie;
+          else --r;
+          const float y2n = P21 * y1 + P22 * y2;
+          y1 = P11 * y1 + insc * (in + drive);
+          y2 = y2n;
+        }
+        if (V >= a.v_th) {
+          V = a.v_reset;
+          r = a.ref_steps;
+          const int lg = (int)(t - a.t_slice0);
+          atomicOr(&mask[lg * Wd + (n >> 5)], 1u << (n & 31));
+        }
+      }
+      a.V[gn] = V;
+      a.r[gn] = r;
+      if (a.model == MODEL_ALPHA) {
+        a.y1[gn] = y1;
+        a.y2[gn] = y2;
+      }
+    }
+  }
+
+  // ---- rows of the window due in later slices go to the HBM ring -------
+  if (a.do_deliver) {
+    const int64_t t_end = a.w_lo + a.Dmax;
+    int64_t t_first = a.t_upd + a.n_upd;
+    if (t_first < a.w_lo) t_first = a.w_lo;
+    for (int64_t t = t_first; t < t_end; ++t) {
+      const int q = (int)(t - a.w_lo);
+      float* rowp = a.rb + (t % a.L) * a.N + j0;
+      const bool add = t < a.rb_hi;
+      for (int n = tid; n < nb; n += kSliceThreads) {
+        const float v = win[q * B + n];
+        if (add) rowp[n] += v;
+        else rowp[n] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- compaction: (lag, neuron)-ordered spike list of this block -------
+  if (a.n_upd > 0) {
+    const int lag0 = (int)(a.t_upd - a.t_slice0);
+    const int nq = a.n_upd * Wd;
+    const int base = a.append ? a.out_cnt[b] : 0;
+    int running = 0;
+    for (int q0 = 0; q0 < nq; q0 += kSliceThreads) {
+      const int q = q0 + tid;
+      uint32_t m = (q < nq) ? mask[lag0 * Wd + q] : 0u;
+      int tot;
+      const int ex = block_excl_scan<int>(__popc(m), scr, tot);
+      if (tot == 0) continue;
+      unsigned long long rbase = 0;
+      if (a.rec) {
+        __shared__ unsigned long long s_rbase;
+        if (tid == 0) s_rbase = atomicAdd(a.rec_n, (unsigned long long)tot);
+        __syncthreads();
+        rbase = s_rbase;
+        __syncthreads();
+      }
+      int pos = running + ex;
+      const int lg = lag0 + q / Wd;
+      const int nbase = (q % Wd) * 32;
+      while (m) {
+        const int bit = __ffs(m) - 1;
+        m &= m - 1;
+        const int64_t gn = j0 + nbase + bit;
+        if (a.write_list) {
+          if (base + pos < a.out_cap)
+            a.out_list[(int64_t)b * a.out_cap + base + pos] = ((uint32_t)gn << 5) | (uint32_t)lg;
+          else
+            atomicOr(a.overflow, 1);
+        }
+        if (a.rec) {
+          const unsigned long long rp = rbase + (unsigned long long)pos - running;
+          if ((int64_t)rp < a.rec_cap) a.rec[rp] = make_uint2((uint32_t)(a.t_slice0 + lg), (uint32_t)gn);
+          else atomicOr(a.overflow, 2);
+        }
+        ++pos;
+      }
+      running += tot;
+    }
+    if (tid == 0) {
+      if (a.write_list) {
+        const int c = base + running;
+        a.out_cnt[b] = c < a.out_cap ? c : a.out_cap;
+      }
+      if (running) atomicAdd(a.spk_count, (unsigned long long)running);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// helpers: ring gap zeroing, open-loop input schedule, decoded export
+// ---------------------------------------------------------------------------
+__global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64_t t_hi) {
+  const int64_t rows = t_hi - t_lo;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * N) return;
+  const int64_t t = t_lo + i / N;
+  rb[(t % L) * N + (i % N)] = 0.f;
+}
+
+__device__ __forceinline__ uint32_t half32(const uint64_t w[4], int64_t t) {
+  const uint64_t x = w[(t & 7) >> 1];
+  return (t & 1) ? (uint32_t)(x >> 32) : (uint32_t)x;
+}
+
+// spikes of every virtual source over [t0, t0 + n_steps), counted per slice
+__global__ void k_input_count(uint64_t seed, int64_t n_src, int64_t t0, int32_t n_steps,
+                              int32_t Dmin, uint32_t thr, int32_t* cnt) {
+  const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_src * n_chunks) return;
+  const int64_t s = i % n_src;
+  const int64_t c = (t0 >> 3) + i / n_src;
+  uint64_t w[4];
+  philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
+  for (int q = 0; q < 8; ++q) {
+    const int64_t t = c * 8 + q;
+    if (t < t0 || t >= t0 + n_steps) continue;
+    if (half32(w, t) < thr) atomicAdd(&cnt[(t - t0) / Dmin], 1);
+  }
+}
+
+__global__ void k_input_fill(uint64_t seed, int64_t n_src, int64_t t0, int32_t n_steps,
+                             int32_t Dmin, uint32_t thr, const int64_t* off, int32_t* cursor,
+                             uint32_t* list) {
+  const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_src * n_chunks) return;
+  const int64_t s = i % n_src;
+  const int64_t c = (t0 >> 3) + i / n_src;
+  uint64_t w[4];
+  philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
+  for (int q = 0; q < 8; ++q) {
+    const int64_t t = c * 8 + q;
+    if (t < t0 || t >= t0 + n_steps) continue;
+    if (half32(w, t) < thr) {
+      const int64_t sl = (t - t0) / Dmin;
+      const int lag = (int)((t - t0) - sl * Dmin);
+      const int p = atomicAdd(&cursor[sl], 1);
+      list[off[sl] + p] = ((uint32_t)s << 5) | (uint32_t)lag;
+    }
+  }
+}
+
+// one thread per (source, block) segment: global target ids and FP32 weights
+__global__ void k_decode_export(const void* syn_tgt, const void* syn_w, int wform,
+                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
+                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
+                                int32_t* tgt_out, float* w_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_src * NB) return;
+  const int64_t src = src_lo + i / NB;
+  const int32_t b = (int32_t)(i % NB);
+  const int64_t cell = src * NB + b;
+  const uint32_t lo = row[cell], hi = row[cell + 1];
+  const uint32_t base = row[src_lo * NB];
+  const float mu = src < src_e_end ? mu_e : mu_i;
+  for (uint32_t e = lo; e < hi; ++e) {
+    float w;
+    int32_t t;
+    if (wform == WF_FP32) {
+      t = ((const int32_t*)syn_tgt)[e];
+      w = ((const float*)syn_w)[e];
+    } else {
+      t = (int32_t)((int64_t)b * B + ((const uint16_t*)syn_tgt)[e]);
+      const float d = __uint_as_float((uint32_t)((const uint16_t*)syn_w)[e] << 16);
+      w = (wform == WF_BF16) ? d : fmaf(mu, d, mu);
+    }
+    tgt_out[e - base] = t;
+    w_out[e - base] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,
+                              double c_m, double i_e, double* p64, float* p32) {
+  hipLaunchKernelGGL(k_propagators, dim3(1), dim3(1), 0, s, model, h, tau_m, tau_syn, c_m, i_e,
+                     p64, p32);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(hipStream_t s, int64_t N, uint64_t seed, double v0_lo, double v0_hi,
+                             float* V, float* y1, float* y2, int32_t* r) {
+  const int nt = 256;
+  const int64_t nbk = (N + nt - 1) / nt;
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)nbk), dim3(nt), 0, s, N, seed, v0_lo, v0_hi, V,
+                     y1, y2, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(hipStream_t s, const BuildArgs& a) {
+  hipLaunchKernelGGL(k_count, dim3((unsigned)a.N), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_sums,
+                       int64_t n_tiles_cap) {
+  const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  if (n_tiles > n_tiles_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
+                     tile_sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sums, n_tiles);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
+                     tile_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t s, const BuildArgs& a) {
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)a.NB), dim3(kFillThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform) {
+  const size_t lds = slice_lds_bytes(a.B, a.Dmin, a.Dmax, a.n_regions);
+  const dim3 grid((unsigned)(8 * a.grid_per_xcd)), block(kSliceThreads);
+  switch (wform) {
+    case WF_FP32:
+      hipLaunchKernelGGL(k_slice<WF_FP32>, grid, block, lds, s, a);
+      break;
+    case WF_BF16:
+      hipLaunchKernelGGL(k_slice<WF_BF16>, grid, block, lds, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(k_slice<WF_BF16_RESID>, grid, block, lds, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t slice_set_lds_limit(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_slice<WF_FP32>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_slice<WF_BF16>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_slice<WF_BF16_RESID>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
+                            int64_t t_hi) {
+  if (t_hi <= t_lo) return hipSuccess;
+  const int64_t n = (t_hi - t_lo) * N;
+  hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rb, N, L,
+                     t_lo, t_hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
+                              int32_t n_steps, int32_t Dmin, uint32_t thr, int32_t* cnt) {
+  const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
+  const int64_t n = n_src * n_chunks;
+  hipLaunchKernelGGL(k_input_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed,
+                     n_src, t0, n_steps, Dmin, thr, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
+                             int32_t n_steps, int32_t Dmin, uint32_t thr, const int64_t* off,
+                             int32_t* cursor, uint32_t* list) {
+  const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
+  const int64_t n = n_src * n_chunks;
+  hipLaunchKernelGGL(k_input_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed,
+                     n_src, t0, n_steps, Dmin, thr, off, cursor, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_export(hipStream_t s, const void* syn_tgt, const void* syn_w, int wform,
+                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
+                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
+                                int32_t* tgt_out, float* w_out) {
+  const int64_t n = n_src * NB;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode_export, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, syn_tgt,
+                     syn_w, wform, row, src_lo, n_src, NB, B, src_e_end, mu_e, mu_i, tgt_out,
+                     w_out);
+  return hipGetLastError();
+}
+
+}  // namespace sd
