@@ -82,7 +82,7 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
         ev_l = (s3["events_delivered"] - s2["events_delivered"]) / n_l
         sp_l = (s3["spikes_delivered"] - s2["spikes_delivered"]) / n_l
     n = net.n_local
-    b_syn = 9 if cfg["wform"] == 0 else 5
+    b_syn = {0: 9, 1: 5, 2: 5, 3: 4}[cfg["wform"]]
     s_state = 16 if cfg["model"] == 1 else 8
     b_alg = algorithmic_bytes(events / steps, spikes / steps, n, d_min, b_syn, s_state)
     out = dict(
@@ -136,7 +136,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000, help="timed slices (1 ms each)")
     ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp32,bf16_resid")
+    ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -151,13 +151,16 @@ def main():
     torch.cuda.set_device(0)
     base = workloads.ALPHA_112K
     forms = {"fp32": dict(base, wform=0, name="alpha_112500_fp32"),
-             "bf16_resid": dict(base, wform=2, name="alpha_112500_bf16_resid")}
+             "bf16": dict(base, wform=1, name="alpha_112500_bf16"),
+             "bf16_resid": dict(base, wform=2, name="alpha_112500_bf16_resid"),
+             "bf16_packed": dict(base, wform=3, name="alpha_112500_bf16_packed")}
     res = {}
     for f in args.forms.split(","):
         _log(f"form {f}")
         res[f] = run_form(forms[f], args.steps, args.warmup)
         _log(json.dumps(res[f]))
-    head = res.get("bf16_resid") or next(iter(res.values()))
+    head_name = next((f for f in ("bf16_packed", "bf16_resid") if f in res), next(iter(res)))
+    head = res[head_name]
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(dict(base, wform=0))
@@ -181,7 +184,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "alpha_112500_k11250_closed_loop", "neurons": 112500,
                    "in_degree": 11250, "synapses": 112500 * 11250, "slice_ms": 1.0,
-                   "weight_storage": "bf16_residual" if head is res.get("bf16_resid") else "fp32",
+                   "weight_storage": head_name,
                    "parallelism": "single_gpu"},
         "achieved_alg_gbs": head["alg_gbs"],
         "forms": res,

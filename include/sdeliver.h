@@ -52,11 +52,20 @@ typedef enum {
 typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
 
 /* Storage form of a synapse (weight, target, delay):
- *   SD_W_FP32       f32 weight, i32 target id, u8 delay       (9 B / synapse)
- *   SD_W_BF16       bf16 weight, u16 offset in block, u8 delay (5 B)
- *   SD_W_BF16_RESID bf16 residual d, w = mu_pop * (1 + d),
- *                   u16 offset in block, u8 delay              (5 B)      */
-typedef enum { SD_W_FP32 = 0, SD_W_BF16 = 1, SD_W_BF16_RESID = 2 } sd_wform;
+ *   SD_W_FP32        f32 weight, i32 target id, u8 delay       (9 B / synapse)
+ *   SD_W_BF16        bf16 weight, u16 offset in block, u8 delay (5 B)
+ *   SD_W_BF16_RESID  bf16 residual d, w = mu_pop * (1 + d), where mu_pop is
+ *                    the FP32 mean weight of the source's population,
+ *                    u16 offset in block, u8 delay              (5 B)
+ *   SD_W_BF16_PACKED the residual weight, an 11-bit offset in block and a
+ *                    5-bit delay - d_min in one 32-bit word     (4 B);
+ *                    needs blocks <= 2048 neurons, d_max - d_min <= 31    */
+typedef enum {
+  SD_W_FP32 = 0,
+  SD_W_BF16 = 1,
+  SD_W_BF16_RESID = 2,
+  SD_W_BF16_PACKED = 3
+} sd_wform;
 
 typedef struct {
   int32_t model;             /* sd_model                                        */
@@ -89,7 +98,7 @@ typedef struct {
   int32_t n_blocks;          /* number of target blocks                         */
   int64_t table_bytes;       /* synapse arrays + segment pointers               */
   int64_t arena_bytes;       /* total device memory of a context                */
-  int32_t bytes_per_synapse; /* 9 (FP32 form) or 5 (BF16 forms)                 */
+  int32_t bytes_per_synapse; /* 9 (FP32), 5 (BF16, BF16 residual), 4 (packed)   */
 } sd_sizes;
 
 typedef struct {
@@ -117,9 +126,10 @@ void sd_destroy(sd_ctx* ctx);
 const char* sd_last_error(const sd_ctx* ctx);
 
 /* Draw the network (one counter-based Philox4x64-10 block per synapse,
- * target-major) and lay it out source-major per target block: for source s
- * and block b the synapses targeting b form one contiguous segment, in
- * (target, draw index) order.  Deterministic; run once before updates. */
+ * target-major) and lay it out block-major: the synapses into target block
+ * b form one contiguous region ordered by source, and for source s the
+ * synapses into b form one contiguous segment in (target, draw index)
+ * order.  Deterministic; run once before updates. */
 sd_status sd_build_connections(sd_ctx* ctx);
 
 /* Advance every neuron by n_steps (1 <= n_steps, and the steps must stay in
@@ -131,11 +141,14 @@ sd_status sd_update_neurons(sd_ctx* ctx, int32_t n_steps);
 
 /* Deliver spikes (Alg. REF result): for every spike (src, lag) and every
  * synapse (src -> j, delay d, weight w): ring[t0 + lag + d][j] += w.
- * d_src/d_lag: n device entries, lag in [0, d_min), src < n_src.  With
- * d_src == NULL the context's own completed slice is delivered and t0 is
- * ignored.  Arrival steps must lie in [t_now, t_now + ring_len). */
+ * d_src/d_lag: n device entries (n == 0: nothing to add), lag in [0, d_min),
+ * src < n_src.  The window [t0 + d_min, t0 + d_min + d_max) of possible
+ * arrival steps must lie in [t_now, t_now + ring_len); otherwise SD_EINVAL. */
 sd_status sd_deliver_spikes(sd_ctx* ctx, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
                             int64_t t0);
+/* Deliver the context's own completed slice (its spikes emitted in the last
+ * d_min steps); SD_ESTATE when no completed slice is pending. */
+sd_status sd_deliver_pending(sd_ctx* ctx);
 
 /* Run round(t_ms / h) steps of the full cycle with fused slice launches
  * (deliver the completed slice, then update the next one).  Resumable:
@@ -170,8 +183,9 @@ sd_status sd_get_pending(sd_ctx* ctx, uint32_t* h_src, uint8_t* h_lag, int64_t c
  * h_row[n_src+1] (int64), h_tgt[n_syn], h_dly[n_syn], h_w[n_syn] */
 sd_status sd_export_connections(sd_ctx* ctx, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
                                 float* h_w);
-/* segment pointers of one source over all blocks: h_ptr[n_blocks+1] */
-sd_status sd_export_segments(sd_ctx* ctx, int64_t src, int64_t* h_ptr);
+/* where one source's segments sit: for every block b, the index of its first
+ * synapse into b and their count (h_start[n_blocks], h_len[n_blocks]) */
+sd_status sd_export_segments(sd_ctx* ctx, int64_t src, int64_t* h_start, int64_t* h_len);
 /* the synapses into target block b, source-major: h_row[n_src+1] (relative
  * to the block's first synapse), then h_tgt/h_dly/h_w of *n_out synapses
  * (h_tgt == NULL: only h_row and *n_out are written) */

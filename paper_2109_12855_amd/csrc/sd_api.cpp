@@ -133,9 +133,8 @@ struct sd_ctx {
   uint32_t* cursor = nullptr;
   uint32_t* tile_sums = nullptr;
   int64_t n_tiles = 0;
-  void* syn_tgt = nullptr;
-  uint8_t* syn_dly = nullptr;
-  void* syn_w = nullptr;
+  void* syn = nullptr;          // synapse records
+  uint8_t* syn_dly = nullptr;   // delays (not used by the packed form)
   float *V = nullptr, *y1 = nullptr, *y2 = nullptr;
   int32_t* r = nullptr;
   float* rb = nullptr;
@@ -162,6 +161,7 @@ struct sd_ctx {
   int32_t n_thr = 0;
   float mu_e = 0.f, mu_i = 0.f;
   int32_t ref_steps = 0;
+  int32_t fx_shift = 0;     // ring window quantum is 2^-fx_shift
   // state machine
   bool built = false;
   int64_t t_now = 0;
@@ -213,7 +213,7 @@ sd_status check_config(const sd_config* c, std::string* why) {
   };
   if (!c) return bad("null config");
   if (c->model != SD_IAF_PSC_DELTA && c->model != SD_IAF_PSC_ALPHA) return bad("unknown model");
-  if (c->wform < SD_W_FP32 || c->wform > SD_W_BF16_RESID) return bad("unknown weight form");
+  if (c->wform < SD_W_FP32 || c->wform > SD_W_BF16_PACKED) return bad("unknown weight form");
   if (c->n_exc < 0 || c->n_inh < 0 || c->n_exc + c->n_inh <= 0) return bad("empty network");
   if (c->k_exc < 0 || c->k_inh < 0) return bad("negative in-degree");
   if (c->k_exc > 0 && (open_loop(*c) ? c->n_src_exc : c->n_exc) <= 0) return bad("no E sources");
@@ -235,8 +235,8 @@ sd_status check_config(const sd_config* c, std::string* why) {
 struct Layout {
   sd_sizes sz;
   int64_t N, n_src, n_syn, M, n_tiles, rec_cap;
-  int32_t B, NB, out_cap, bps_w, bps_t;
-  size_t off_row, off_cursor, off_tiles, off_tgt, off_dly, off_w, off_V, off_y1, off_y2, off_r,
+  int32_t B, NB, out_cap, rec_bytes, dly_bytes;
+  size_t off_row, off_cursor, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt0, off_cnt1, off_rec, off_wte, off_wti, off_thr,
       off_p64, off_p32, off_counters, off_overflow, total;
 };
@@ -254,6 +254,11 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     *why = "u16 offsets need blocks of at most 65536 neurons";
     return SD_EINVAL;
   }
+  if (c->wform == SD_W_BF16_PACKED &&
+      (L->B > (1 << kPackOffBits) || c->d_max - c->d_min >= (1 << kPackDlyBits))) {
+    *why = "packed form needs blocks of at most 2048 neurons and d_max - d_min < 32";
+    return SD_EUNSUPPORTED;
+  }
   const size_t lds = slice_lds_bytes(L->B, c->d_min, c->d_max, L->NB);
   if (lds > 160 * 1024) {
     *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
@@ -269,8 +274,8 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->rec_cap = c->record_spikes ? (c->record_cap > 0 ? c->record_cap
                                                      : std::max<int64_t>(1 << 20, L->N * 64))
                                 : 0;
-  L->bps_w = c->wform == SD_W_FP32 ? 4 : 2;
-  L->bps_t = c->wform == SD_W_FP32 ? 4 : 2;
+  L->rec_bytes = c->wform == SD_W_FP32 ? 8 : 4;
+  L->dly_bytes = c->wform == SD_W_BF16_PACKED ? 0 : 1;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -280,9 +285,8 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_row = take((size_t)L->M * 4);
   L->off_cursor = take((size_t)L->M * 4);
   L->off_tiles = take((size_t)L->n_tiles * 4);
-  L->off_tgt = take((size_t)L->n_syn * L->bps_t);
-  L->off_dly = take((size_t)L->n_syn);
-  L->off_w = take((size_t)L->n_syn * L->bps_w);
+  L->off_syn = take((size_t)L->n_syn * L->rec_bytes);
+  L->off_dly = take((size_t)L->n_syn * L->dly_bytes);
   L->off_V = take((size_t)L->N * 4);
   L->off_y1 = take((size_t)L->N * 4);
   L->off_y2 = take((size_t)L->N * 4);
@@ -307,7 +311,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   z.n_syn = L->n_syn;
   z.block_neurons = L->B;
   z.n_blocks = L->NB;
-  z.bytes_per_synapse = c->wform == SD_W_FP32 ? 9 : 5;
+  z.bytes_per_synapse = L->rec_bytes + L->dly_bytes;
   z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * 4;
   z.arena_bytes = (int64_t)L->total;
   return SD_OK;
@@ -323,9 +327,9 @@ SliceArgs base_args(sd_ctx* c) {
   std::memset(&a, 0, sizeof a);
   const sd_config& g = c->cfg;
   a.row = c->row;
-  a.syn_tgt = c->syn_tgt;
+  a.n_src = c->n_src;
+  a.syn = c->syn;
   a.syn_dly = c->syn_dly;
-  a.syn_w = c->syn_w;
   a.N = c->N;
   a.NB = c->NB;
   a.B = c->B;
@@ -336,6 +340,8 @@ SliceArgs base_args(sd_ctx* c) {
   a.mu_e = c->mu_e;
   a.mu_i = c->mu_i;
   a.count_mode = c->count_mode;
+  a.fx_scale = std::ldexp(1.0f, c->fx_shift);
+  a.fx_inv = std::ldexp(1.0, -c->fx_shift);
   a.grid_per_xcd = c->grid_per_xcd;
   a.V = c->V;
   a.y1 = c->y1;
@@ -374,6 +380,33 @@ sd_status fill_gap(sd_ctx* c, int64_t w_lo) {
     c->rb_hi = w_lo;
   }
   return SD_OK;
+}
+
+// Decode record e of a host copy of the synapse arrays (b: its block).
+void decode_record(const sd_config& g, const uint8_t* rec, const uint8_t* dl, uint32_t e,
+                   int32_t b, int32_t B, float mu, int32_t* tgt, float* w, uint8_t* dly) {
+  if (g.wform == SD_W_FP32) {
+    uint64_t r;
+    std::memcpy(&r, rec + (size_t)e * 8, 8);
+    const uint32_t wb = (uint32_t)r;
+    std::memcpy(w, &wb, 4);
+    *tgt = (int32_t)(r >> 32);
+    *dly = dl[e];
+    return;
+  }
+  uint32_t r;
+  std::memcpy(&r, rec + (size_t)e * 4, 4);
+  const uint32_t u = r << 16;
+  float d;
+  std::memcpy(&d, &u, 4);
+  *w = g.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
+  if (g.wform == SD_W_BF16_PACKED) {
+    *tgt = (int32_t)((int64_t)b * B + ((r >> 16) & ((1u << kPackOffBits) - 1)));
+    *dly = (uint8_t)(g.d_min + (int)(r >> (16 + kPackOffBits)));
+  } else {
+    *tgt = (int32_t)((int64_t)b * B + (r >> 16));
+    *dly = dl[e];
+  }
 }
 
 // Point the delivery arguments at the completed slice's spikes: the
@@ -457,9 +490,8 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->row = (uint32_t*)(A + L.off_row);
   c->cursor = (uint32_t*)(A + L.off_cursor);
   c->tile_sums = (uint32_t*)(A + L.off_tiles);
-  c->syn_tgt = A + L.off_tgt;
+  c->syn = A + L.off_syn;
   c->syn_dly = (uint8_t*)(A + L.off_dly);
-  c->syn_w = A + L.off_w;
   c->V = (float*)(A + L.off_V);
   c->y1 = (float*)(A + L.off_y1);
   c->y2 = (float*)(A + L.off_y2);
@@ -487,6 +519,21 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->mu_i = (float)(-g.g * g.w_exc);
   c->n_thr = poisson_table(g.drive_rate_hz * g.h * 1e-3, c->thr_h, kMaxThr);
   c->ref_steps = (int32_t)std::llround(g.t_ref / g.h);
+  // Fixed-point quantum of the LDS window: the largest 2^-s with
+  // max|w| * 2^s <= 2^30, so one synapse's code fits int32 with margin and
+  // 64-bit cell sums cannot overflow for fewer than 2^32 events per cell.
+  {
+    double wmax = 1.0;  // count mode delivers 1.0
+    if (g.w_cv == 0.0) {
+      wmax = std::max({wmax, std::fabs(g.w_exc), std::fabs(g.g * g.w_exc)});
+    } else {
+      for (int i = 0; i < 65536; ++i)
+        wmax = std::max({wmax, (double)std::fabs(c->we_h[i]), (double)std::fabs(c->wi_h[i])});
+      wmax *= 1.01;  // BF16 decoding may round up by < 2^-8
+    }
+    int s = (int)std::floor(std::log2(1073741824.0 / wmax));
+    c->fx_shift = std::max(0, std::min(s, 40));
+  }
   std::vector<uint32_t> enc_e(65536), enc_i(65536);
   for (int i = 0; i < 65536; ++i) {
     if (g.wform == SD_W_FP32) {
@@ -495,7 +542,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
     } else if (g.wform == SD_W_BF16) {
       enc_e[i] = bf16_bits_rne(c->we_h[i]);
       enc_i[i] = bf16_bits_rne(c->wi_h[i]);
-    } else {
+    } else {  // residual forms (plain and packed)
       enc_e[i] = resid_bits(c->we_h[i], c->mu_e);
       enc_i[i] = resid_bits(c->wi_h[i], c->mu_i);
     }
@@ -522,8 +569,13 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
                                 c->prop64, c->prop32));
   HIP_TRY(c, launch_init_state(c->stream, c->N, g.seed, g.v0_lo, g.v0_hi, c->V, c->y1, c->y2,
                                c->r));
-  HIP_TRY(c, slice_set_lds_limit(160 * 1024));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int lds_max = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max, c->NB) + 64;
+  if ((size_t)lds_max < lds)
+    return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
+                lds_max);
   return SD_OK;
 }
 
@@ -564,10 +616,10 @@ sd_status sd_build_connections(sd_ctx* c) {
   a.seed = g.seed;
   a.row = c->row;
   a.cursor = c->cursor;
-  a.syn_tgt = c->syn_tgt;
+  a.syn = c->syn;
   a.syn_dly = c->syn_dly;
-  a.syn_w = c->syn_w;
   a.wform = g.wform;
+  a.d_min = g.d_min;
   a.wtab_e = c->wtab_e;
   a.wtab_i = c->wtab_i;
   a.fixed = g.w_cv == 0.0;
@@ -577,7 +629,7 @@ sd_status sd_build_connections(sd_ctx* c) {
   if (g.wform == SD_W_BF16) {
     a.fix_bits_e = bf16_bits_rne(fe);
     a.fix_bits_i = bf16_bits_rne(fi);
-  } else if (g.wform == SD_W_BF16_RESID) {
+  } else if (g.wform == SD_W_BF16_RESID || g.wform == SD_W_BF16_PACKED) {
     a.fix_bits_e = resid_bits(fe, c->mu_e);
     a.fix_bits_i = resid_bits(fi, c->mu_i);
   }
@@ -642,9 +694,26 @@ sd_status sd_update_neurons(sd_ctx* c, int32_t n_steps) {
   return SD_OK;
 }
 
+namespace {
+sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t* d_lag,
+                       int64_t n, int64_t t0);
+}
+
 sd_status sd_deliver_spikes(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
                             int64_t t0) {
   if (!c) return SD_EINVAL;
+  if (n < 0 || (n > 0 && (!d_src || !d_lag))) return fail(c, SD_EINVAL, "bad spike list");
+  return deliver_impl(c, false, d_src, d_lag, n, t0);
+}
+
+sd_status sd_deliver_pending(sd_ctx* c) {
+  if (!c) return SD_EINVAL;
+  return deliver_impl(c, true, nullptr, nullptr, 0, 0);
+}
+
+namespace {
+sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t* d_lag,
+                       int64_t n, int64_t t0) {
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   const sd_config& g = c->cfg;
   SliceArgs a = base_args(c);
@@ -653,14 +722,13 @@ sd_status sd_deliver_spikes(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_l
   a.t_upd = c->t_now;
   uint32_t* packed = nullptr;
   int32_t* d_n = nullptr;
-  if (d_src == nullptr) {
+  if (own) {
     if (!c->pend_open || c->t_now % g.d_min != 0 || c->t_now != c->pend_t0 + g.d_min)
       return fail(c, SD_ESTATE, "no completed slice to deliver");
     t0 = c->pend_t0;
     sd_status s = set_pending_input(c, a);
     if (s != SD_OK) return s;
   } else {
-    if (n < 0 || !d_lag) return fail(c, SD_EINVAL, "bad spike list");
     if (t0 + g.d_min < c->t_now)
       return fail(c, SD_EINVAL, "arrivals at step %lld precede t_now %lld",
                   (long long)(t0 + g.d_min), (long long)c->t_now);
@@ -711,9 +779,10 @@ sd_status sd_deliver_spikes(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_l
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipFree(packed));
   }
-  if (d_src == nullptr) c->pend_open = false;
+  if (own) c->pend_open = false;
   return SD_OK;
 }
+}  // namespace
 
 sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
   if (!c || n_steps < 0) return fail(c, SD_EINVAL, "bad step count");
@@ -917,38 +986,59 @@ sd_status sd_get_pending(sd_ctx* c, uint32_t* h_src, uint8_t* h_lag, int64_t cap
   return SD_OK;
 }
 
+// Host-side gather of the whole table into canonical (source, target, draw)
+// order: meant for small networks (tests); large ones use sd_export_block.
 sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
                                 float* h_w) {
   if (!c || !h_row) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  // per-source rows from the (source, block) pointers
   std::vector<uint32_t> rp((size_t)c->M);
   HIP_TRY(c, hipMemcpy(rp.data(), c->row, (size_t)c->M * 4, hipMemcpyDeviceToHost));
-  for (int64_t s = 0; s <= c->n_src; ++s) h_row[s] = rp[(size_t)(s * c->NB)];
+  const int64_t S = c->n_src;
+  h_row[0] = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    int64_t deg = 0;
+    for (int32_t b = 0; b < c->NB; ++b) deg += rp[(size_t)(b * S + s + 1)] - rp[(size_t)(b * S + s)];
+    h_row[s + 1] = h_row[s] + deg;
+  }
   if (!h_tgt && !h_dly && !h_w) return SD_OK;
-  int32_t* d_t = nullptr;
-  float* d_w = nullptr;
-  HIP_TRY(c, hipMalloc((void**)&d_t, (size_t)std::max<int64_t>(c->n_syn, 1) * 4));
-  HIP_TRY(c, hipMalloc((void**)&d_w, (size_t)std::max<int64_t>(c->n_syn, 1) * 4));
-  HIP_TRY(c, launch_decode_export(c->stream, c->syn_tgt, c->syn_w, c->cfg.wform, c->row, 0,
-                                  c->n_src, c->NB, c->B, c->src_e_end, c->mu_e, c->mu_i, d_t, d_w));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (h_tgt) HIP_TRY(c, hipMemcpy(h_tgt, d_t, (size_t)c->n_syn * 4, hipMemcpyDeviceToHost));
-  if (h_w) HIP_TRY(c, hipMemcpy(h_w, d_w, (size_t)c->n_syn * 4, hipMemcpyDeviceToHost));
-  if (h_dly) HIP_TRY(c, hipMemcpy(h_dly, c->syn_dly, (size_t)c->n_syn, hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipFree(d_t));
-  HIP_TRY(c, hipFree(d_w));
+  const sd_config& g = c->cfg;
+  const int rb = g.wform == SD_W_FP32 ? 8 : 4;
+  std::vector<uint8_t> rec((size_t)c->n_syn * rb), dl((size_t)c->n_syn);
+  if (c->n_syn) {
+    HIP_TRY(c, hipMemcpy(rec.data(), c->syn, rec.size(), hipMemcpyDeviceToHost));
+    if (g.wform != SD_W_BF16_PACKED)
+      HIP_TRY(c, hipMemcpy(dl.data(), c->syn_dly, dl.size(), hipMemcpyDeviceToHost));
+  }
+  for (int64_t s = 0; s < S; ++s) {
+    int64_t at = h_row[s];
+    const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
+    for (int32_t b = 0; b < c->NB; ++b) {
+      for (uint32_t e = rp[(size_t)(b * S + s)]; e < rp[(size_t)(b * S + s + 1)]; ++e, ++at) {
+        int32_t t;
+        float w;
+        uint8_t d;
+        decode_record(g, rec.data(), dl.data(), e, b, c->B, mu, &t, &w, &d);
+        if (h_tgt) h_tgt[at] = t;
+        if (h_w) h_w[at] = w;
+        if (h_dly) h_dly[at] = d;
+      }
+    }
+  }
   return SD_OK;
 }
 
-sd_status sd_export_segments(sd_ctx* c, int64_t src, int64_t* h_ptr) {
-  if (!c || !h_ptr || src < 0 || src >= c->n_src) return SD_EINVAL;
+sd_status sd_export_segments(sd_ctx* c, int64_t src, int64_t* h_start, int64_t* h_len) {
+  if (!c || !h_start || !h_len || src < 0 || src >= c->n_src) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<uint32_t> rp((size_t)c->NB + 1);
-  HIP_TRY(c, hipMemcpy(rp.data(), c->row + src * c->NB, rp.size() * 4, hipMemcpyDeviceToHost));
-  for (int32_t b = 0; b <= c->NB; ++b) h_ptr[b] = rp[(size_t)b];
+  for (int32_t b = 0; b < c->NB; ++b) {
+    uint32_t p[2];
+    HIP_TRY(c, hipMemcpy(p, c->row + (size_t)b * c->n_src + src, 8, hipMemcpyDeviceToHost));
+    h_start[b] = p[0];
+    h_len[b] = (int64_t)p[1] - p[0];
+  }
   return SD_OK;
 }
 
@@ -969,7 +1059,7 @@ sd_status sd_host_tables(const sd_config* cfg, float* h_we, float* h_wi, uint32_
       const uint32_t be = (uint32_t)bf16_bits_rne(we[i]) << 16, bi = (uint32_t)bf16_bits_rne(wi[i]) << 16;
       std::memcpy(&we[i], &be, 4);
       std::memcpy(&wi[i], &bi, 4);
-    } else if (cfg->wform == SD_W_BF16_RESID) {
+    } else if (cfg->wform == SD_W_BF16_RESID || cfg->wform == SD_W_BF16_PACKED) {
       const uint32_t de = (uint32_t)resid_bits(we[i], mu_e) << 16, di = (uint32_t)resid_bits(wi[i], mu_i) << 16;
       float fe, fi;
       std::memcpy(&fe, &de, 4);
@@ -992,46 +1082,25 @@ sd_status sd_export_block(sd_ctx* c, int32_t b, int64_t* h_row, int32_t* h_tgt, 
   if (!c || !h_row || b < 0 || b >= c->NB) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  // pointers of column b: row[s * NB + b], row[s * NB + b + 1]
-  std::vector<uint32_t> rp((size_t)c->M);
-  HIP_TRY(c, hipMemcpy(rp.data(), c->row, (size_t)c->M * 4, hipMemcpyDeviceToHost));
-  std::vector<uint32_t> lo((size_t)c->n_src), len((size_t)c->n_src);
-  int64_t tot = 0;
-  h_row[0] = 0;
-  for (int64_t s = 0; s < c->n_src; ++s) {
-    lo[s] = rp[(size_t)(s * c->NB + b)];
-    len[s] = rp[(size_t)(s * c->NB + b + 1)] - lo[s];
-    tot += len[s];
-    h_row[s + 1] = tot;
-  }
+  const int64_t S = c->n_src;
+  std::vector<uint32_t> rp((size_t)S + 1);
+  HIP_TRY(c, hipMemcpy(rp.data(), c->row + (size_t)b * S, rp.size() * 4, hipMemcpyDeviceToHost));
+  for (int64_t s = 0; s <= S; ++s) h_row[s] = (int64_t)rp[(size_t)s] - rp[0];
+  const int64_t tot = h_row[S];
   if (n_out) *n_out = tot;
-  if (!h_tgt) return SD_OK;
-  const int bt = c->cfg.wform == SD_W_FP32 ? 4 : 2;
-  for (int64_t s = 0; s < c->n_src; ++s) {
-    if (!len[s]) continue;
-    const int64_t at = h_row[s];
-    std::vector<uint8_t> tb((size_t)len[s] * bt), wb((size_t)len[s] * bt);
-    HIP_TRY(c, hipMemcpy(tb.data(), (char*)c->syn_tgt + (size_t)lo[s] * bt, tb.size(),
-                         hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(wb.data(), (char*)c->syn_w + (size_t)lo[s] * bt, wb.size(),
-                         hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(h_dly + at, c->syn_dly + lo[s], (size_t)len[s], hipMemcpyDeviceToHost));
+  if (!h_tgt || tot == 0) return SD_OK;
+  const sd_config& g = c->cfg;
+  const int rb = g.wform == SD_W_FP32 ? 8 : 4;
+  std::vector<uint8_t> rec((size_t)tot * rb), dl((size_t)tot);
+  HIP_TRY(c, hipMemcpy(rec.data(), (char*)c->syn + (size_t)rp[0] * rb, rec.size(),
+                       hipMemcpyDeviceToHost));
+  if (g.wform != SD_W_BF16_PACKED)
+    HIP_TRY(c, hipMemcpy(dl.data(), c->syn_dly + rp[0], dl.size(), hipMemcpyDeviceToHost));
+  for (int64_t s = 0; s < S; ++s) {
     const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
-    for (uint32_t i = 0; i < len[s]; ++i) {
-      if (bt == 4) {
-        std::memcpy(&h_tgt[at + i], &tb[(size_t)i * 4], 4);
-        std::memcpy(&h_w[at + i], &wb[(size_t)i * 4], 4);
-      } else {
-        uint16_t o, wbits;
-        std::memcpy(&o, &tb[(size_t)i * 2], 2);
-        std::memcpy(&wbits, &wb[(size_t)i * 2], 2);
-        h_tgt[at + i] = (int32_t)((int64_t)b * c->B + o);
-        const uint32_t u = (uint32_t)wbits << 16;
-        float d;
-        std::memcpy(&d, &u, 4);
-        h_w[at + i] = c->cfg.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
-      }
-    }
+    for (int64_t e = h_row[s]; e < h_row[s + 1]; ++e)
+      decode_record(g, rec.data(), dl.data(), (uint32_t)e, b, c->B, mu, &h_tgt[e], &h_w[e],
+                    &h_dly[e]);
   }
   return SD_OK;
 }

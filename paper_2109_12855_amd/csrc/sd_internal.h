@@ -10,26 +10,39 @@ namespace sd {
 
 enum { STREAM_SYN = 1, STREAM_INIT = 2, STREAM_DRIVE = 3, STREAM_SRC = 4 };
 enum { MODEL_DELTA = 0, MODEL_ALPHA = 1 };
-enum { WF_FP32 = 0, WF_BF16 = 1, WF_BF16_RESID = 2 };
+enum { WF_FP32 = 0, WF_BF16 = 1, WF_BF16_RESID = 2, WF_PACKED = 3 };
 
 constexpr int kMaxThr = 64;        // Poisson-drive threshold table entries
 constexpr int kSliceThreads = 1024;  // threads of a slice workgroup
 constexpr int kFillThreads = 512;    // threads of a build workgroup
 constexpr int kFillChunk = 2048;     // draws ranked per build iteration
 
+// Synapse record layouts (one record per synapse, plus a u8 delay array for
+// the first three forms):
+//   WF_FP32        u64: low word FP32 weight bits, high word i32 target id
+//   WF_BF16        u32: low half BF16 weight, high half u16 offset in block
+//   WF_BF16_RESID  u32: low half BF16 residual d (w = mu (1 + d)), high half
+//                  u16 offset in block
+//   WF_PACKED      u32: bits 0-15 BF16 residual, 16-26 offset in block,
+//                  27-31 delay - d_min (no delay array)
+constexpr int kPackOffBits = 11;
+constexpr int kPackDlyBits = 5;
+
 // Everything a slice launch needs (passed by value).
 struct SliceArgs {
   // network layout
-  const uint32_t* row;     // [n_src * NB + 1] segment pointers, source-major
-  const void* syn_tgt;     // i32 target id (FP32 form) or u16 offset in block
-  const uint8_t* syn_dly;  // u8 delay in steps
-  const void* syn_w;       // f32 weight, bf16 weight or bf16 residual
+  const uint32_t* row;     // [NB * n_src + 1] segment pointers, block-major
+  int64_t n_src;           // source ids
+  const void* syn;         // synapse records (layout per weight form)
+  const uint8_t* syn_dly;  // u8 delay in steps (not used by the packed form)
   int64_t N;               // local neurons
   int32_t NB, B;           // blocks, neurons per block
   int32_t Dmin, Dmax, L;
   int64_t src_e_end;       // source ids below this are excitatory
   float mu_e, mu_i;        // population means of the residual form
   int32_t count_mode;      // deliver 1.0 per synapse
+  float fx_scale;          // 2^s: weights enter the LDS window as round(w * 2^s)
+  double fx_inv;           // 2^-s
   int32_t grid_per_xcd;    // blocks handled by one XCD (ceil(NB / 8))
   // delivery
   int32_t do_deliver;
@@ -80,10 +93,10 @@ struct BuildArgs {
   uint64_t seed;
   uint32_t* row;           // counts, then exclusive scan
   uint32_t* cursor;        // fill cursors (copy of row)
-  void* syn_tgt;
+  void* syn;
   uint8_t* syn_dly;
-  void* syn_w;
   int32_t wform;
+  int32_t d_min;
   const void* wtab_e;      // encoded weight per quantile index (f32 or bf16 bits)
   const void* wtab_i;
   float w_fix_e, w_fix_i;  // fixed weights (cv == 0), encoded at use
@@ -109,10 +122,5 @@ hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64
 hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
                              int32_t n_steps, int32_t Dmin, uint32_t thr, const int64_t* off,
                              int32_t* cursor, uint32_t* list);
-hipError_t launch_decode_export(hipStream_t s, const void* syn_tgt, const void* syn_w, int wform,
-                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
-                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
-                                int32_t* tgt_out, float* w_out);
-hipError_t slice_set_lds_limit(size_t bytes);
 
 }  // namespace sd

@@ -11,10 +11,12 @@
 //   window that are due in later slices are written to the ring in HBM.
 //
 // Build (once, untimed, Sec. 2.2):
-//   k_count / scan / k_fill lay out the source-major, block-partitioned
-//   table: segment (src, b) holds the synapses from src into block b in
-//   (target, draw) order.  k_fill ranks equal sources inside each chunk of
-//   draws with an LDS bitonic sort, so the layout is deterministic.
+//   k_count / scan / k_fill lay out the block-major table: the synapses into
+//   target block b occupy one contiguous region, ordered by source, and
+//   segment (src, b) holds those from src in (target, draw) order.  A
+//   workgroup therefore only ever reads its own block's region, which keeps
+//   its address translations local.  k_fill ranks equal sources inside each
+//   chunk of draws with an LDS bitonic sort, so the layout is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "sd_internal.h"
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(256) k_count(BuildArgs a) {
   const int32_t b = (int32_t)(j / a.B);
   for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
     const Draw d = draw_synapse(a, j, k);
-    atomicAdd(&a.row[(int64_t)d.src * a.NB + b], 1u);
+    atomicAdd(&a.row[(int64_t)b * a.n_src + d.src], 1u);
   }
 }
 
@@ -265,25 +267,26 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
       const int idx = (int)(key & 2047);
       int rank = 0;
       while (p - rank - 1 >= 0 && (uint32_t)(keys[p - rank - 1] >> 11) == src) ++rank;
-      const int64_t cell = (int64_t)src * a.NB + b;
+      const int64_t cell = (int64_t)b * a.n_src + src;
       const int64_t pos = (int64_t)a.cursor[cell] + rank;
       const uint32_t m = meta[idx];
       const uint32_t widx = m & 0xffffu, inh = (m >> 16) & 1u, dly = m >> 24;
       const int64_t jl = (c0 + idx) / a.K;
-      a.syn_dly[pos] = (uint8_t)dly;
       if (a.wform == WF_FP32) {
-        ((int32_t*)a.syn_tgt)[pos] = (int32_t)(j0 + jl);
         float w;
         if (a.fixed) w = inh ? a.w_fix_i : a.w_fix_e;
         else w = inh ? ((const float*)a.wtab_i)[widx] : ((const float*)a.wtab_e)[widx];
-        ((float*)a.syn_w)[pos] = w;
+        ((uint64_t*)a.syn)[pos] =
+            ((uint64_t)(uint32_t)(j0 + jl) << 32) | (uint64_t)__float_as_uint(w);
       } else {
-        ((uint16_t*)a.syn_tgt)[pos] = (uint16_t)jl;
-        uint16_t wb;
-        if (a.fixed) wb = (uint16_t)(inh ? a.fix_bits_i : a.fix_bits_e);
+        uint32_t wb;
+        if (a.fixed) wb = inh ? a.fix_bits_i : a.fix_bits_e;
         else wb = inh ? ((const uint16_t*)a.wtab_i)[widx] : ((const uint16_t*)a.wtab_e)[widx];
-        ((uint16_t*)a.syn_w)[pos] = wb;
+        uint32_t rec = (wb & 0xffffu) | ((uint32_t)jl << 16);
+        if (a.wform == WF_PACKED) rec |= (uint32_t)(dly - a.d_min) << (16 + kPackOffBits);
+        ((uint32_t*)a.syn)[pos] = rec;
       }
+      if (a.wform != WF_PACKED) a.syn_dly[pos] = (uint8_t)dly;
     }
     __syncthreads();
     for (int p = tid; p < n_in; p += kFillThreads) {
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
       if (last) {
         int run = 1;
         while (p - run >= 0 && (uint32_t)(keys[p - run] >> 11) == src) ++run;
-        a.cursor[(int64_t)src * a.NB + b] += (uint32_t)run;
+        a.cursor[(int64_t)b * a.n_src + src] += (uint32_t)run;
       }
     }
     __syncthreads();
@@ -302,35 +305,69 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
 // ---------------------------------------------------------------------------
 // the fused slice kernel
 // ---------------------------------------------------------------------------
+// Synapse base + i (base wave-uniform): offset in the block, delay - d_min
+// and the decoded FP32 weight.
 template <int WF>
-__device__ __forceinline__ float syn_weight(const void* w, int64_t e, float mu) {
+__device__ __forceinline__ void syn_load(const void* syn, const uint8_t* dly, uint32_t base, int i,
+                                         int32_t j0, int Dmin, float mu, int& off, int& dd,
+                                         float& w) {
   if constexpr (WF == WF_FP32) {
-    return ((const float*)w)[e];
-  } else if constexpr (WF == WF_BF16) {
-    return __uint_as_float((uint32_t)((const uint16_t*)w)[e] << 16);
+    const uint64_t r = ((const uint64_t*)syn + base)[i];
+    w = __uint_as_float((uint32_t)r);
+    off = (int)(r >> 32) - j0;
+    dd = (int)(dly + base)[i] - Dmin;
+  } else if constexpr (WF == WF_PACKED) {
+    const uint32_t r = ((const uint32_t*)syn + base)[i];
+    const float d = __uint_as_float(r << 16);
+    w = fmaf(mu, d, mu);
+    off = (int)((r >> 16) & ((1u << kPackOffBits) - 1));
+    dd = (int)(r >> (16 + kPackOffBits));
   } else {
-    const float d = __uint_as_float((uint32_t)((const uint16_t*)w)[e] << 16);
-    return fmaf(mu, d, mu);
+    const uint32_t r = ((const uint32_t*)syn + base)[i];
+    const float d = __uint_as_float(r << 16);
+    w = (WF == WF_BF16) ? d : fmaf(mu, d, mu);
+    off = (int)(r >> 16);
+    dd = (int)(dly + base)[i] - Dmin;
   }
 }
 
-template <int WF>
-__device__ __forceinline__ int syn_offset(const void* t, int64_t e, int32_t j0) {
-  if constexpr (WF == WF_FP32) return ((const int32_t*)t)[e] - j0;
-  else return (int)((const uint16_t*)t)[e];
+
+// Fixed-point quantum of the LDS ring window: a weight w enters as the
+// integer round(w * 2^s); sums are exact 64-bit integers (LDS integer
+// atomics are ~10x faster than float atomics on gfx950, and the result no
+// longer depends on the order of the adds).
+__device__ __forceinline__ long long to_fixed(float w, float scale) {
+  return (long long)__float2int_rn(w * scale);
+}
+__device__ __forceinline__ float from_fixed(long long q, double inv) {
+  return (float)((double)q * inv);
 }
 
-__device__ __forceinline__ int rl_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-__device__ __forceinline__ float rl_f(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+// LDS layout of a slice workgroup (byte offsets, 16-byte aligned pieces)
+struct SliceLds {
+  size_t win, carry, dcnt, mask, thr, pre, scr, desc, total;
+};
+__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax, int n_regions) {
+  auto up = [](size_t x) { return (x + 15) / 16 * 16; };
+  SliceLds L;
+  size_t o = 0;
+  L.win = o;   o = up(o + (size_t)Dmax * B * 8);        // int64 ring window
+  L.carry = o; o = up(o + (size_t)Dmin * B * 4);        // staged HBM rows (FP32)
+  L.dcnt = o;  o = up(o + (size_t)Dmin * B);            // Poisson-drive counts (u8)
+  L.mask = o;  o = up(o + (size_t)Dmin * (B / 32) * 4); // spike bitmask
+  L.thr = o;   o = up(o + (size_t)kMaxThr * 4);         // drive thresholds
+  L.pre = o;   o = up(o + (size_t)(n_regions + 1) * 4); // spike-list region prefix
+  L.scr = o;   o = up(o + (size_t)(kSliceThreads / 64 + 1) * 4);
+  L.desc = o;  o = up(o + (size_t)kSliceThreads * 16);   // per-wave spike descriptors
+  L.total = o;
+  return L;
 }
 
 size_t slice_lds_bytes(int B, int Dmin, int Dmax, int n_regions) {
-  return (size_t)Dmax * B * 4 + (size_t)Dmin * (B / 32) * 4 + (size_t)(n_regions + 1) * 4 +
-         (size_t)(kSliceThreads / 64 + 1) * 4 + 16;
+  return slice_lds_layout(B, Dmin, Dmax, n_regions).total;
 }
 
-constexpr int kUnroll = 8;
+constexpr int kUnroll = 16;
 
 template <int WF>
 __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
@@ -348,20 +385,95 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   const int64_t j0 = (int64_t)b * B;
   const int nb = (int)((a.N - j0) < B ? (a.N - j0) : B);
   const int Wd = B >> 5;
+  const int Dmin = a.Dmin;
 
-  float* win = (float*)lds_raw;
-  uint32_t* mask = (uint32_t*)(win + (size_t)a.Dmax * B);
-  int32_t* pre = (int32_t*)(mask + (size_t)a.Dmin * Wd);
-  int32_t* scr = pre + a.n_regions + 1;
+  const SliceLds Lo = slice_lds_layout(B, Dmin, a.Dmax, a.n_regions);
+  long long* win = (long long*)(lds_raw + Lo.win);
+  float* carry = (float*)(lds_raw + Lo.carry);
+  uint8_t* dcnt = lds_raw + Lo.dcnt;
+  uint32_t* mask = (uint32_t*)(lds_raw + Lo.mask);
+  uint32_t* thr = (uint32_t*)(lds_raw + Lo.thr);
+  int32_t* pre = (int32_t*)(lds_raw + Lo.pre);
+  int32_t* scr = (int32_t*)(lds_raw + Lo.scr);
+  // descriptor of spike s0 + u of this wave's batch: {segment start, length,
+  // lag, population mean weight}, read back by all lanes as an LDS broadcast
+  uint4* desc = (uint4*)(lds_raw + Lo.desc) + wv * 64;
 
-  if (a.do_deliver) {
-    for (int i = tid; i < a.Dmax * B; i += kSliceThreads) win[i] = 0.f;
+  // window rows cover steps [w_lo, w_lo + Dmax)
+  const int64_t w_lo = a.w_lo;
+  if (a.do_deliver)
+    for (int i = tid; i < a.Dmax * B; i += kSliceThreads) win[i] = 0;
+  for (int i = tid; i < Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
+  if (tid < kMaxThr) thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xffffffffu;
+
+  // ---- prologue: issue the loads the update will need -------------------
+  // Carried ring rows (deliveries of earlier slices) and this thread's
+  // neuron state are loaded into registers now; they arrive while the
+  // spikes are delivered.
+  constexpr int kRows = 16;
+  int rows = 0;
+  if (a.n_upd > 0) {
+    int64_t t_hi = a.t_upd + a.n_upd;
+    if (t_hi > a.rb_hi) t_hi = a.rb_hi;
+    rows = (int)(t_hi > a.t_upd ? t_hi - a.t_upd : 0);
   }
-  for (int i = tid; i < a.Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
+  const int r0 = (int)(a.t_upd % a.L);
+  const bool fast = rows > 0 && rows <= kRows && nb <= kSliceThreads;
+  const int n_own = tid < nb ? tid : nb - 1;  // in-bounds neuron of this thread
+  float stage[kRows];
+  if (fast) {
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      int rr = r0 + (q < rows ? q : 0);
+      if (rr >= a.L) rr -= a.L;
+      stage[q] = a.rb[(int64_t)rr * a.N + j0 + n_own];
+    }
+  }
+  float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
+  int sr = 0;
+  if (a.n_upd > 0) {
+    sV = a.V[j0 + n_own];
+    sr = a.r[j0 + n_own];
+    if (a.model == MODEL_ALPHA) {
+      sy1 = a.y1[j0 + n_own];
+      sy2 = a.y2[j0 + n_own];
+    }
+  }
+
+  // Poisson drive of the steps to update: one Philox4x64-10 block per
+  // (neuron, 8-step chunk) gives eight 32-bit uniforms; the count is the
+  // number of CDF thresholds at or below each uniform.  Round k covers tasks
+  // k*1024 + tid; rounds are interleaved with the delivery loads below.
+  int64_t c0 = 0;
+  int n_tasks = 0;
+  if (a.n_upd > 0) {
+    c0 = a.t_upd >> 3;
+    const int64_t c1 = (a.t_upd + a.n_upd - 1) >> 3;
+    n_tasks = (int)(c1 - c0 + 1) * nb;
+  }
+  const int n_rounds = (n_tasks + kSliceThreads - 1) / kSliceThreads;
+  auto drive_round = [&](int k) {
+    const int task = k * kSliceThreads + tid;
+    if (task >= n_tasks) return;
+    const int n = task % nb;
+    const int64_t c = c0 + task / nb;
+    uint64_t rr[4];
+    philox(a.seed, STREAM_DRIVE, (uint64_t)(j0 + n), (uint64_t)c, rr);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t t = c * 8 + q;
+      if (t < a.t_upd || t >= a.t_upd + a.n_upd) continue;
+      const uint64_t word = rr[q >> 1];
+      const uint32_t u = (q & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+      int cnt = 0;
+      while (cnt < a.n_thr && u >= thr[cnt]) ++cnt;  // thresholds ascend
+      dcnt[(int)(t - a.t_upd) * B + n] = (uint8_t)cnt;
+    }
+  };
+  int rounds_done = 0;
 
   // ---- deliver the completed slice into the LDS window (Alg. REF) -------
   if (a.do_deliver) {
-    // prefix of region counts
     const int R = a.n_regions;
     const int per = (R + kSliceThreads - 1) / kSliceThreads;
     int s = 0;
@@ -370,7 +482,7 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
       if (r < R) s += a.in_cnt[r];
     }
     int tot;
-    int ex = block_excl_scan<int>(s, scr, tot);
+    int ex = block_excl_scan<int>(s, scr, tot);  // also orders thr / zeroing
     for (int q = 0; q < per; ++q) {
       const int r = tid * per + q;
       if (r < R) {
@@ -381,26 +493,36 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     if (tid == 0) pre[R] = tot;
     __syncthreads();
     const int64_t total = tot;
+    const float fx = a.count_mode ? 0.f : a.fx_scale;
+    const long long one_q = (long long)a.fx_scale;  // count mode: 1.0 per synapse
 
+    // Every wave takes an equal contiguous share of the spikes.  Each block
+    // starts at a different point of the list (the sums are exact integers,
+    // so the order is free): otherwise all blocks would read the same
+    // relative offsets of their equally sized regions at the same moment.
+    const int64_t rot = total > 0 ? ((int64_t)b * 7919) % total : 0;
+    const int64_t per_w = (total + nwv - 1) / nwv;
+    const int64_t w_beg = (int64_t)wv * per_w;
+    const int64_t w_end = (w_beg + per_w) < total ? (w_beg + per_w) : total;
     uint64_t ev = 0;
-    const int Dmin = a.Dmin;
-    for (int64_t base = (int64_t)wv * 64; base < total; base += (int64_t)nwv * 64) {
+    for (int64_t base = w_beg; base < w_end; base += 64) {
       const int64_t i = base + lane;
       uint32_t lo = 0;
       int len = 0, lag = 0;
       float mu = 0.f;
-      if (i < total) {
+      if (i < w_end) {
+        const int64_t ir = (i + rot) < total ? i + rot : i + rot - total;
         int rlo = 0, rhi = R;
         while (rhi - rlo > 1) {
           const int m = (rlo + rhi) >> 1;
-          if (pre[m] <= i) rlo = m;
+          if (pre[m] <= ir) rlo = m;
           else rhi = m;
         }
-        const uint32_t ent = a.in_list[(int64_t)rlo * a.in_cap + (i - pre[rlo])];
+        const uint32_t ent = a.in_list[(int64_t)rlo * a.in_cap + (ir - pre[rlo])];
         const uint32_t src = ent >> 5;
         lag = (int)(ent & 31u);
         if (lag < Dmin) {
-          const int64_t p = (int64_t)src * a.NB + b;
+          const int64_t p = (int64_t)b * a.n_src + src;
           lo = a.row[p];
           len = (int)(a.row[p + 1] - lo);
           mu = ((int64_t)src < a.src_e_end) ? a.mu_e : a.mu_i;
@@ -409,57 +531,91 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
         }
       }
       ev += (uint64_t)len;
-      const int n_here = (int)((total - base) < 64 ? (total - base) : 64);
+      desc[lane] = make_uint4(lo, (uint32_t)len, (uint32_t)lag, __float_as_uint(mu));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int n_here = (int)((w_end - base) < 64 ? (w_end - base) : 64);
       for (int s0 = 0; s0 < n_here; s0 += kUnroll) {
-        uint32_t slo[kUnroll];
-        int slen[kUnroll], sslot[kUnroll];
-        float smu[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          slo[u] = (uint32_t)rl_i((int)lo, s0 + u);
-          slen[u] = rl_i(len, s0 + u);
-          sslot[u] = rl_i(lag, s0 + u) - Dmin;
-          smu[u] = rl_f(mu, s0 + u);
-        }
+        // Branch-free loads: lanes past a segment's end re-read its last
+        // element (an empty segment reads element 0), so all kUnroll segment
+        // loads issue back to back; only the LDS adds are predicated.
         int off[kUnroll], dl[kUnroll];
         float w[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (lane < slen[u]) {
-            const int64_t e = (int64_t)slo[u] + lane;
-            off[u] = syn_offset<WF>(a.syn_tgt, e, (int32_t)j0);
-            dl[u] = a.syn_dly[e];
-            w[u] = syn_weight<WF>(a.syn_w, e, smu[u]);
-          }
+          const uint4 d = desc[s0 + u];
+          const int sl = (int)d.y;
+          const int li = lane < sl ? lane : (sl > 0 ? sl - 1 : 0);
+          const uint32_t sb = sl > 0 ? d.x : 0u;
+          syn_load<WF>(a.syn, a.syn_dly, sb, li, (int32_t)j0, Dmin, __uint_as_float(d.w), off[u],
+                       dl[u], w[u]);
         }
+        // ALU work while the loads are in flight
+        if (rounds_done < n_rounds) drive_round(rounds_done++);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (lane < slen[u]) {
-            const float v = a.count_mode ? 1.f : w[u];
-            __hip_atomic_fetch_add(&win[(sslot[u] + dl[u]) * B + off[u]], v, __ATOMIC_RELAXED,
+          const uint4 d = desc[s0 + u];
+          if (lane < (int)d.y) {
+            const long long v = a.count_mode ? one_q : to_fixed(w[u], fx);
+            __hip_atomic_fetch_add((unsigned long long*)&win[((int)d.z + dl[u]) * B + off[u]],
+                                   (unsigned long long)v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
         // segments longer than one wave
         for (int u = 0; u < kUnroll; ++u) {
-          for (int e0 = 64; e0 < slen[u]; e0 += 64) {
-            if (lane + e0 < slen[u]) {
-              const int64_t e = (int64_t)slo[u] + e0 + lane;
-              const int o = syn_offset<WF>(a.syn_tgt, e, (int32_t)j0);
-              const int d = a.syn_dly[e];
-              const float v = a.count_mode ? 1.f : syn_weight<WF>(a.syn_w, e, smu[u]);
-              __hip_atomic_fetch_add(&win[(sslot[u] + d) * B + o], v, __ATOMIC_RELAXED,
+          const uint4 d = desc[s0 + u];
+          for (int e0 = 64; e0 < (int)d.y; e0 += 64) {
+            if (lane + e0 < (int)d.y) {
+              int o, dd;
+              float wl;
+              syn_load<WF>(a.syn, a.syn_dly, d.x, e0 + lane, (int32_t)j0, Dmin,
+                           __uint_as_float(d.w), o, dd, wl);
+              const long long v = a.count_mode ? one_q : to_fixed(wl, fx);
+              __hip_atomic_fetch_add((unsigned long long*)&win[((int)d.z + dd) * B + o],
+                                     (unsigned long long)v, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
             }
           }
         }
       }
+      // the next batch overwrites the descriptors
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // events of this wave
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
     if (lane == 0 && ev) atomicAdd(a.ev_count, (unsigned long long)ev);
     if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+  } else {
+    __syncthreads();  // thr / zeroing visible
+  }
+  while (rounds_done < n_rounds) drive_round(rounds_done++);
+
+  // staged rows into LDS
+  if (a.n_upd > 0) {
+    if (fast) {
+      if (tid < nb) {
+#pragma unroll
+        for (int q = 0; q < kRows; ++q)
+          if (q < rows) carry[q * B + tid] = stage[q];
+      }
+    } else {
+      for (int i = tid; i < rows * nb; i += kSliceThreads) {
+        const int q = i / nb, n = i - q * nb;
+        int rr = r0 + q;
+        while (rr >= a.L) rr -= a.L;
+        carry[q * B + n] = a.rb[(int64_t)rr * a.N + j0 + n];
+      }
+    }
+    // rows at or past rb_hi hold no earlier input
+    for (int i = tid; i < (a.n_upd - rows) * nb; i += kSliceThreads) {
+      const int q = rows + i / nb, n = i - (i / nb) * nb;
+      carry[q * B + n] = 0.f;
+    }
   }
   __syncthreads();
 
@@ -467,35 +623,50 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   if (a.n_upd > 0) {
     const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
     const float P32 = a.prop[4], P33 = a.prop[5], P30Ie = a.prop[6], insc = a.prop[7];
-    const int L = a.L;
+    const double inv = a.fx_inv;
     for (int n = tid; n < nb; n += kSliceThreads) {
       const int64_t gn = j0 + n;
-      float V = a.V[gn];
-      int r = a.r[gn];
-      float y1 = 0.f, y2 = 0.f;
-      if (a.model == MODEL_ALPHA) {
-        y1 = a.y1[gn];
-        y2 = a.y2[gn];
+      float V, y1 = 0.f, y2 = 0.f;
+      int r;
+      if (n == tid) {
+        V = sV;
+        r = sr;
+        y1 = sy1;
+        y2 = sy2;
+      } else {
+        V = a.V[gn];
+        r = a.r[gn];
+        if (a.model == MODEL_ALPHA) {
+          y1 = a.y1[gn];
+          y2 = a.y2[gn];
+        }
       }
-      uint64_t rr[4] = {0, 0, 0, 0};
-      int64_t chunk = -1;
-      for (int s = 0; s < a.n_upd; ++s) {
+      // inputs of up to 16 steps are read from LDS up front (independent
+      // reads), then the steps run on registers
+      constexpr int kSteps = 16;
+      const int qw = (int)(a.t_upd - w_lo);  // window row of the first step
+      for (int s0 = 0; s0 < a.n_upd; s0 += kSteps) {
+        float in_s[kSteps], dr_s[kSteps];
+#pragma unroll
+        for (int q = 0; q < kSteps; ++q) {
+          const int s = s0 + q;
+          float in = 0.f, dr = 0.f;
+          if (s < a.n_upd) {
+            in = carry[s * B + n];
+            dr = (float)dcnt[s * B + n] * a.drive_w;
+            if (a.do_deliver && qw + s >= 0 && qw + s < a.Dmax)
+              in += from_fixed(win[(qw + s) * B + n], inv);
+          }
+          in_s[q] = in;
+          dr_s[q] = dr;
+        }
+#pragma unroll
+        for (int q = 0; q < kSteps; ++q) {
+        const int s = s0 + q;
+        if (s >= a.n_upd) break;
         const int64_t t = a.t_upd + s;
-        float in = 0.f;
-        if (t < a.rb_hi) in = a.rb[(t % L) * a.N + gn];
-        if (a.do_deliver) {
-          const int64_t q = t - a.w_lo;
-          if (q >= 0 && q < a.Dmax) in += win[q * B + n];
-        }
-        if ((t >> 3) != chunk) {
-          chunk = t >> 3;
-          philox(a.seed, STREAM_DRIVE, (uint64_t)gn, (uint64_t)chunk, rr);
-        }
-        const uint64_t word = rr[(t & 7) >> 1];
-        const uint32_t u = (t & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-        int c = 0;
-        for (int k = 0; k < a.n_thr; ++k) c += (u >= a.thr[k]) ? 1 : 0;
-        const float drive = (float)c * a.drive_w;
+        const float in = in_s[q];
+        const float drive = dr_s[q];
         if (a.model == MODEL_DELTA) {
           if (r > 0) --r;
           else V = a.e_l + P33 * (V - a.e_l) + P30Ie + in + drive;
@@ -512,6 +683,7 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
           const int lg = (int)(t - a.t_slice0);
           atomicOr(&mask[lg * Wd + (n >> 5)], 1u << (n & 31));
         }
+        }
       }
       a.V[gn] = V;
       a.r[gn] = r;
@@ -524,15 +696,16 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
 
   // ---- rows of the window due in later slices go to the HBM ring -------
   if (a.do_deliver) {
-    const int64_t t_end = a.w_lo + a.Dmax;
+    const double inv = a.fx_inv;
+    const int64_t t_end = w_lo + a.Dmax;
     int64_t t_first = a.t_upd + a.n_upd;
-    if (t_first < a.w_lo) t_first = a.w_lo;
+    if (t_first < w_lo) t_first = w_lo;
     for (int64_t t = t_first; t < t_end; ++t) {
-      const int q = (int)(t - a.w_lo);
+      const int q = (int)(t - w_lo);
       float* rowp = a.rb + (t % a.L) * a.N + j0;
       const bool add = t < a.rb_hi;
       for (int n = tid; n < nb; n += kSliceThreads) {
-        const float v = win[q * B + n];
+        const float v = from_fixed(win[q * B + n], inv);
         if (add) rowp[n] += v;
         else rowp[n] = v;
       }
@@ -647,35 +820,6 @@ __global__ void k_input_fill(uint64_t seed, int64_t n_src, int64_t t0, int32_t n
   }
 }
 
-// one thread per (source, block) segment: global target ids and FP32 weights
-__global__ void k_decode_export(const void* syn_tgt, const void* syn_w, int wform,
-                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
-                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
-                                int32_t* tgt_out, float* w_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_src * NB) return;
-  const int64_t src = src_lo + i / NB;
-  const int32_t b = (int32_t)(i % NB);
-  const int64_t cell = src * NB + b;
-  const uint32_t lo = row[cell], hi = row[cell + 1];
-  const uint32_t base = row[src_lo * NB];
-  const float mu = src < src_e_end ? mu_e : mu_i;
-  for (uint32_t e = lo; e < hi; ++e) {
-    float w;
-    int32_t t;
-    if (wform == WF_FP32) {
-      t = ((const int32_t*)syn_tgt)[e];
-      w = ((const float*)syn_w)[e];
-    } else {
-      t = (int32_t)((int64_t)b * B + ((const uint16_t*)syn_tgt)[e]);
-      const float d = __uint_as_float((uint32_t)((const uint16_t*)syn_w)[e] << 16);
-      w = (wform == WF_BF16) ? d : fmaf(mu, d, mu);
-    }
-    tgt_out[e - base] = t;
-    w_out[e - base] = w;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -727,22 +871,14 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform) {
     case WF_BF16:
       hipLaunchKernelGGL(k_slice<WF_BF16>, grid, block, lds, s, a);
       break;
+    case WF_PACKED:
+      hipLaunchKernelGGL(k_slice<WF_PACKED>, grid, block, lds, s, a);
+      break;
     default:
       hipLaunchKernelGGL(k_slice<WF_BF16_RESID>, grid, block, lds, s, a);
       break;
   }
   return hipGetLastError();
-}
-
-hipError_t slice_set_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_slice<WF_FP32>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_slice<WF_BF16>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_slice<WF_BF16_RESID>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
@@ -773,16 +909,5 @@ hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_decode_export(hipStream_t s, const void* syn_tgt, const void* syn_w, int wform,
-                                const uint32_t* row, int64_t src_lo, int64_t n_src, int32_t NB,
-                                int32_t B, int64_t src_e_end, float mu_e, float mu_i,
-                                int32_t* tgt_out, float* w_out) {
-  const int64_t n = n_src * NB;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decode_export, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, syn_tgt,
-                     syn_w, wform, row, src_lo, n_src, NB, B, src_e_end, mu_e, mu_i, tgt_out,
-                     w_out);
-  return hipGetLastError();
-}
 
 }  // namespace sd

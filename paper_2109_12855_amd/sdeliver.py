@@ -19,7 +19,7 @@ SD_OK, SD_EINVAL, SD_ENOMEM, SD_EHIP, SD_EOVERFLOW, SD_ESTATE, SD_EUNSUPPORTED =
 STATUS_NAMES = {0: "SD_OK", -1: "SD_EINVAL", -2: "SD_ENOMEM", -3: "SD_EHIP", -4: "SD_EOVERFLOW",
                 -5: "SD_ESTATE", -6: "SD_EUNSUPPORTED"}
 SD_IAF_PSC_DELTA, SD_IAF_PSC_ALPHA = 0, 1
-SD_W_FP32, SD_W_BF16, SD_W_BF16_RESID = 0, 1, 2
+SD_W_FP32, SD_W_BF16, SD_W_BF16_RESID, SD_W_BF16_PACKED = 0, 1, 2, 3
 
 
 class SdError(RuntimeError):
@@ -72,7 +72,7 @@ class sd_stats(C.Structure):
 # every symbol include/sdeliver.h declares
 EXPORTS = (
     "sd_query_sizes", "sd_create", "sd_destroy", "sd_last_error", "sd_build_connections",
-    "sd_update_neurons", "sd_deliver_spikes", "sd_simulate", "sd_simulate_steps",
+    "sd_update_neurons", "sd_deliver_spikes", "sd_deliver_pending", "sd_simulate", "sd_simulate_steps",
     "sd_set_count_mode", "sd_prepare_input", "sd_t_now", "sd_get_sizes", "sd_get_stats",
     "sd_read_ring", "sd_read_state", "sd_write_state", "sd_get_spikes", "sd_get_pending",
     "sd_export_connections", "sd_export_segments", "sd_export_block", "sd_get_tables",
@@ -99,6 +99,7 @@ def lib():
         "sd_build_connections": ([vp], i32),
         "sd_update_neurons": ([vp, i32], i32),
         "sd_deliver_spikes": ([vp, vp, vp, i64, i64], i32),
+        "sd_deliver_pending": ([vp], i32),
         "sd_simulate": ([vp, dbl], i32),
         "sd_simulate_steps": ([vp, i64], i32),
         "sd_set_count_mode": ([vp, i32], i32),
@@ -112,7 +113,7 @@ def lib():
         "sd_get_spikes": ([vp, vp, vp, i64, P(i64)], i32),
         "sd_get_pending": ([vp, vp, vp, i64, P(i64), P(i64)], i32),
         "sd_export_connections": ([vp, vp, vp, vp, vp], i32),
-        "sd_export_segments": ([vp, i64, vp], i32),
+        "sd_export_segments": ([vp, i64, vp, vp], i32),
         "sd_get_tables": ([vp, vp, vp, vp, P(i32), vp, vp], i32),
         "sd_export_block": ([vp, i32, vp, vp, vp, vp, P(i64)], i32),
         "sd_host_tables": ([P(sd_config), vp, vp, vp, P(i32)], i32),
@@ -175,7 +176,9 @@ class Net:
     the fused slice cycle; ``update`` / ``deliver`` expose the two phases.
     """
 
-    def __init__(self, cfg: dict, stream=None, **over):
+    def __init__(self, cfg: dict, stream=None, torch_arena: bool = True, **over):
+        """torch_arena: carve the context's device memory out of one torch
+        tensor (default) or let the library allocate it with hipMalloc."""
         import torch
 
         self.cfg = dict(cfg)
@@ -184,12 +187,14 @@ class Net:
         self.sizes = query_sizes(self.cfg)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.arena = torch.empty(int(self.sizes["arena_bytes"]), dtype=torch.uint8,
-                                 device=self.device)
+        self.arena = None
+        if torch_arena:
+            self.arena = torch.empty(int(self.sizes["arena_bytes"]), dtype=torch.uint8,
+                                     device=self.device)
         h = C.c_void_p()
         rc = lib().sd_create(C.byref(self._c), C.c_void_p(self.stream.cuda_stream),
-                             C.c_void_p(self.arena.data_ptr()), int(self.arena.numel()),
-                             C.byref(h))
+                             C.c_void_p(self.arena.data_ptr()) if torch_arena else None,
+                             int(self.arena.numel()) if torch_arena else 0, C.byref(h))
         self._h = h
         if rc != SD_OK:
             msg = lib().sd_last_error(h).decode() if h else ""
@@ -230,7 +235,7 @@ class Net:
         """Deliver a device spike list (torch uint32-as-int32 / uint8 tensors), or
         the context's completed slice when ``src`` is None."""
         if src is None:
-            rc = lib().sd_deliver_spikes(self._h, None, None, 0, 0)
+            rc = lib().sd_deliver_pending(self._h)
         else:
             rc = lib().sd_deliver_spikes(self._h, _ptr(src), _ptr(lag), int(src.numel()), int(t0))
         self._check(rc, "sd_deliver_spikes")
@@ -324,10 +329,14 @@ class Net:
                                           C.byref(n)), "sd_export_block")
         return row, tgt, dly, w
 
-    def segments(self, src: int) -> np.ndarray:
-        out = np.zeros(int(self.sizes["n_blocks"]) + 1, np.int64)
-        self._check(lib().sd_export_segments(self._h, int(src), _ptr(out)), "sd_export_segments")
-        return out
+    def segments(self, src: int):
+        """(start, length) of source src's segment in every target block."""
+        nb = int(self.sizes["n_blocks"])
+        start = np.zeros(nb, np.int64)
+        length = np.zeros(nb, np.int64)
+        self._check(lib().sd_export_segments(self._h, int(src), _ptr(start), _ptr(length)),
+                    "sd_export_segments")
+        return start, length
 
     def tables(self) -> dict:
         we = np.zeros(65536, np.float32)

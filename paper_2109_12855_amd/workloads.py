@@ -74,6 +74,10 @@ ALPHA_112K = dict(
 )
 
 ALPHA_112K_BF16 = dict(ALPHA_112K, name="alpha_112500_bf16", wform=2)
+ALPHA_112K_PACKED = dict(ALPHA_112K, name="alpha_112500_bf16_packed", wform=3)
+
+# the oracle decodes the packed form's weights exactly like the residual form
+ORACLE_WFORM = {0: 0, 1: 1, 2: 2, 3: 2}
 
 # One GPU's share of a brain-scale net: 1,125,000 local targets whose
 # 11,250 sources each come from a virtual 10M population (8M E, 2M I) that

@@ -35,11 +35,11 @@ def _tiny_cases():
 # build
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("case", range(5))
-@pytest.mark.parametrize("wform", [0, 1, 2])
+@pytest.mark.parametrize("wform", [0, 1, 2, 3])
 def test_connections_bit_exact(case, wform):
     cfg = dict(_tiny_cases()[case], wform=wform)
     net = sdeliver.Net(cfg).build()
-    ref = oracle.Net(cfg)
+    ref = oracle.Net(cfg, wform=W.ORACLE_WFORM[wform])
     row, tgt, dly, w = net.connections()
     orow, otgt, odly, ow = ref.source_major()
     assert np.array_equal(row, orow)
@@ -82,7 +82,8 @@ def test_tables_propagators_initial_state():
 # --------------------------------------------------------------------------
 def _replay_check(cfg, src, lag, t0=0):
     net = sdeliver.Net(cfg).build()
-    ref = oracle.Net(cfg)
+    ocfg = dict(cfg, wform=W.ORACLE_WFORM[cfg.get("wform", 0)])
+    ref = oracle.Net(ocfg)
     d_src, d_lag = _dev(src, lag)
     net.set_count_mode(True)
     net.deliver(d_src, d_lag, t0)
@@ -95,7 +96,7 @@ def _replay_check(cfg, src, lag, t0=0):
     rb = net2.ring().astype(np.float64)
     ref_rb = ref.ring()
     # sum |w| per cell bounds the FP32 accumulation error
-    ref_abs = oracle.Net(cfg)
+    ref_abs = oracle.Net(ocfg)
     row, tgt, dly, w = ref_abs.source_major()
     absw = np.zeros_like(ref_rb)
     L = cfg["ring_len"]
@@ -118,7 +119,7 @@ def test_replay_delivery(case):
     _replay_check(cfg, src, lag)
 
 
-@pytest.mark.parametrize("wform", [1, 2])
+@pytest.mark.parametrize("wform", [1, 2, 3])
 def test_replay_delivery_bf16_forms(wform):
     cfg = dict(_tiny_cases()[4], wform=wform)
     src, lag = W.replay_spikes(2111, 700, cfg["d_min"], seed=11)
@@ -135,9 +136,39 @@ def test_replay_edge_cases():
     _replay_check(cfg, src, lag)
     # only the last source, last lag
     _replay_check(cfg, np.array([n - 1], np.uint32), np.array([cfg["d_min"] - 1], np.uint8))
-    # nonzero t0 (arrivals wrap around the ring)
+    # nonzero t0: the window [t0 + d_min, t0 + d_min + d_max) must fit the ring
     src, lag = W.replay_spikes(n, 300, cfg["d_min"], seed=2)
-    _replay_check(cfg, src, lag, t0=7)
+    _replay_check(cfg, src, lag, t0=2)
+
+
+def test_replay_window_beyond_ring_rejected():
+    cfg = _tiny_cases()[3]
+    net = sdeliver.Net(cfg).build()
+    s, l = _dev(np.array([5], np.uint32), np.array([0], np.uint8))
+    with pytest.raises(sdeliver.SdError) as e:
+        net.deliver(s, l, 7)  # window ends at 37 > t_now + ring_len = 32
+    assert e.value.status == sdeliver.SD_EINVAL
+
+
+def test_replay_wraps_around_ring():
+    """After two slices the delivery window wraps past the ring's end."""
+    # silent neurons (no drive, V0 = 0): count mode must not feed dynamics
+    cfg = dict(_tiny_cases()[3], drive_rate_hz=0.0, v0_lo=0.0, v0_hi=0.0)
+    n = 1000
+    net = sdeliver.Net(cfg).build()
+    ref = oracle.Net(cfg)
+    net.set_count_mode(True)
+    d = cfg["d_min"]
+    for k in range(2):
+        net.update(d)
+        assert len(net.pending()[0]) == 0
+        net.deliver()
+        st, idx = ref.update(d)
+        assert len(st) == 0
+    src, lag = W.replay_spikes(n, 400, d, seed=9)
+    net.deliver(*_dev(src, lag), 2 * d - d)   # window [2d, 2d + d_max) wraps mod 32
+    ref.deliver(src, lag, d)
+    assert np.array_equal(net.ring().astype(np.int64), ref.counts().astype(np.int64))
 
 
 def test_replay_empty_list_and_errors():
