@@ -405,6 +405,11 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     for (int i = tid; i < a.Dmax * B; i += kSliceThreads) win[i] = 0;
   for (int i = tid; i < Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
   if (tid < kMaxThr) thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xffffffffu;
+  // events of this block, summed in LDS: one global atomic per workgroup
+  // (thousands of same-address global atomics per launch back up the
+  // memory queues of every compute unit)
+  __shared__ unsigned long long s_ev;
+  if (tid == 0) s_ev = 0;
 
   // ---- prologue: issue the loads the update will need -------------------
   // Carried ring rows (deliveries of earlier slices) and this thread's
@@ -588,8 +593,9 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     // events of this wave
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
-    if (lane == 0 && ev) atomicAdd(a.ev_count, (unsigned long long)ev);
-    if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+    if (lane == 0 && ev)
+      __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     __syncthreads();  // thr / zeroing visible
   }
@@ -618,6 +624,10 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     }
   }
   __syncthreads();
+  if (tid == 0 && a.do_deliver) {
+    if (s_ev) atomicAdd(a.ev_count, s_ev);
+    if (b == 0) atomicAdd(a.spk_in_count, (unsigned long long)pre[a.n_regions]);
+  }
 
   // ---- update the next slice's steps (exact propagation, Sec. 2.1) -------
   if (a.n_upd > 0) {
