@@ -57,9 +57,10 @@ typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
  *   SD_W_BF16_RESID  bf16 residual d, w = mu_pop * (1 + d), where mu_pop is
  *                    the FP32 mean weight of the source's population,
  *                    u16 offset in block, u8 delay              (5 B)
- *   SD_W_BF16_PACKED the residual weight, an 11-bit offset in block and a
- *                    5-bit delay - d_min in one 32-bit word     (4 B);
- *                    needs blocks <= 2048 neurons, d_max - d_min <= 31    */
+ *   SD_W_BF16_PACKED the residual weight (low half) and the ring-window slot
+ *                    (delay - d_min) * block_neurons + offset in block
+ *                    (high half) in one 32-bit word             (4 B);
+ *                    needs (d_max - d_min + 1) * block_neurons <= 65536   */
 typedef enum {
   SD_W_FP32 = 0,
   SD_W_BF16 = 1,
@@ -129,14 +130,17 @@ const char* sd_last_error(const sd_ctx* ctx);
  * target-major) and lay it out block-major: the synapses into target block
  * b form one contiguous region ordered by source, and for source s the
  * synapses into b form one contiguous segment in (target, draw index)
- * order.  Deterministic; run once before updates. */
+ * order; the segment pointers are stored source-major as (start, count)
+ * pairs.  Deterministic; run once before updates. */
 sd_status sd_build_connections(sd_ctx* ctx);
 
 /* Advance every neuron by n_steps (1 <= n_steps, and the steps must stay in
  * the current slice of d_min steps): reads and consumes the ring buffer
  * rows of those steps, draws the Poisson drive, propagates exactly, applies
  * threshold/reset/refractoriness, and appends emitted spikes to the open
- * slice's spike list (ordered by (lag, target block, neuron)). */
+ * slice's spike list (one contiguous list; each block appends its spikes in
+ * (lag, neuron) order, blocks in any order - delivery sums are exact
+ * integers, so the order does not change results). */
 sd_status sd_update_neurons(sd_ctx* ctx, int32_t n_steps);
 
 /* Deliver spikes (Alg. REF result): for every spike (src, lag) and every

@@ -126,11 +126,13 @@ struct sd_ctx {
   std::string err;
   // geometry
   int64_t N = 0, n_src = 0, n_syn = 0, src_e_end = 0;
-  int32_t B = 0, NB = 0, K = 0, grid_per_xcd = 0, out_cap = 0;
+  int32_t B = 0, NB = 0, K = 0, grid_per_xcd = 0;
+  int64_t list_cap = 0;  // entries of a slice's spike list
   int64_t M = 0;  // entries of the segment-pointer table
   // device buffers
-  uint32_t* row = nullptr;
+  uint32_t* row = nullptr;      // block-major segment starts
   uint32_t* cursor = nullptr;
+  uint2* seg = nullptr;         // source-major (start, count) pairs
   uint32_t* tile_sums = nullptr;
   int64_t n_tiles = 0;
   void* syn = nullptr;          // synapse records
@@ -139,7 +141,11 @@ struct sd_ctx {
   int32_t* r = nullptr;
   float* rb = nullptr;
   uint32_t* list[2] = {nullptr, nullptr};
-  int32_t* list_cnt[2] = {nullptr, nullptr};
+  // list counters rotate over three words: the open slice's (ci), the next
+  // one (always zero between calls) and the one before (cleared by the next
+  // fused launch)
+  int32_t* cnt3 = nullptr;
+  int ci = 0;
   uint2* rec = nullptr;
   int64_t rec_cap = 0;
   void* wtab_e = nullptr;
@@ -235,10 +241,11 @@ sd_status check_config(const sd_config* c, std::string* why) {
 struct Layout {
   sd_sizes sz;
   int64_t N, n_src, n_syn, M, n_tiles, rec_cap;
-  int32_t B, NB, out_cap, rec_bytes, dly_bytes;
-  size_t off_row, off_cursor, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
-      off_rb, off_list0, off_list1, off_cnt0, off_cnt1, off_rec, off_wte, off_wti, off_thr,
-      off_p64, off_p32, off_counters, off_overflow, total;
+  int32_t B, NB, rec_bytes, dly_bytes;
+  int64_t list_cap;
+  size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
+      off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
+      off_counters, off_overflow, total;
 };
 
 sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
@@ -254,12 +261,19 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     *why = "u16 offsets need blocks of at most 65536 neurons";
     return SD_EINVAL;
   }
-  if (c->wform == SD_W_BF16_PACKED &&
-      (L->B > (1 << kPackOffBits) || c->d_max - c->d_min >= (1 << kPackDlyBits))) {
-    *why = "packed form needs blocks of at most 2048 neurons and d_max - d_min < 32";
+  if (c->wform == SD_W_BF16_PACKED && (int64_t)(c->d_max - c->d_min + 1) * L->B > 65536) {
+    *why = "packed form needs (d_max - d_min + 1) * block_neurons <= 65536";
     return SD_EUNSUPPORTED;
   }
-  const size_t lds = slice_lds_bytes(L->B, c->d_min, c->d_max, L->NB);
+  // a block's synapses are read through buffer resources whose "nothing to
+  // load" offset (element 2^28) must lie past the end: at most 2^28
+  // synapses and 2^30 record bytes per block
+  if ((int64_t)L->B * K > (1LL << 28) ||
+      (int64_t)L->B * K * (c->wform == SD_W_FP32 ? 8 : 4) > (1LL << 30)) {
+    *why = "a target block holds more than 2^28 synapses or 1 GiB; lower block_neurons";
+    return SD_EUNSUPPORTED;
+  }
+  const size_t lds = slice_lds_bytes(L->B, c->d_min, c->d_max);
   if (lds > 160 * 1024) {
     *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
     return SD_EUNSUPPORTED;
@@ -270,7 +284,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     return SD_EUNSUPPORTED;
   }
   L->n_tiles = (L->M + 4095) / 4096;
-  L->out_cap = L->B * c->d_min;
+  L->list_cap = (int64_t)L->NB * L->B * c->d_min;
   L->rec_cap = c->record_spikes ? (c->record_cap > 0 ? c->record_cap
                                                      : std::max<int64_t>(1 << 20, L->N * 64))
                                 : 0;
@@ -284,6 +298,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   };
   L->off_row = take((size_t)L->M * 4);
   L->off_cursor = take((size_t)L->M * 4);
+  L->off_seg = take((size_t)L->n_src * L->NB * 8);
   L->off_tiles = take((size_t)L->n_tiles * 4);
   L->off_syn = take((size_t)L->n_syn * L->rec_bytes);
   L->off_dly = take((size_t)L->n_syn * L->dly_bytes);
@@ -292,10 +307,9 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_y2 = take((size_t)L->N * 4);
   L->off_r = take((size_t)L->N * 4);
   L->off_rb = take((size_t)c->ring_len * L->N * 4);
-  L->off_list0 = take((size_t)L->NB * L->out_cap * 4);
-  L->off_list1 = take((size_t)L->NB * L->out_cap * 4);
-  L->off_cnt0 = take((size_t)L->NB * 4);
-  L->off_cnt1 = take((size_t)L->NB * 4);
+  L->off_list0 = take((size_t)L->list_cap * 4);
+  L->off_list1 = take((size_t)L->list_cap * 4);
+  L->off_cnt = take(3 * 4);
   L->off_rec = take((size_t)std::max<int64_t>(L->rec_cap, 1) * 8);
   L->off_wte = take(65536 * 4);
   L->off_wti = take(65536 * 4);
@@ -312,7 +326,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   z.block_neurons = L->B;
   z.n_blocks = L->NB;
   z.bytes_per_synapse = L->rec_bytes + L->dly_bytes;
-  z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * 4;
+  z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * 4 + L->n_src * L->NB * 8;
   z.arena_bytes = (int64_t)L->total;
   return SD_OK;
 }
@@ -326,10 +340,11 @@ SliceArgs base_args(sd_ctx* c) {
   SliceArgs a;
   std::memset(&a, 0, sizeof a);
   const sd_config& g = c->cfg;
-  a.row = c->row;
+  a.seg = c->seg;
   a.n_src = c->n_src;
   a.syn = c->syn;
   a.syn_dly = c->syn_dly;
+  a.K = c->K;
   a.N = c->N;
   a.NB = c->NB;
   a.B = c->B;
@@ -337,10 +352,22 @@ SliceArgs base_args(sd_ctx* c) {
   a.Dmax = g.d_max;
   a.L = g.ring_len;
   a.src_e_end = c->src_e_end;
-  a.mu_e = c->mu_e;
-  a.mu_i = c->mu_i;
-  a.count_mode = c->count_mode;
-  a.fx_scale = std::ldexp(1.0f, c->fx_shift);
+  {
+    // fixed-point weight trunc(m1 * x + m0): x is the weight (FP32, BF16) or
+    // the BF16 residual (w = mu (1 + x)); count mode adds 1.0 per synapse
+    const float sc = std::ldexp(1.0f, c->fx_shift);
+    const bool resid = g.wform == SD_W_BF16_RESID || g.wform == SD_W_BF16_PACKED;
+    if (c->count_mode) {
+      a.wm0_e = a.wm0_i = sc;
+      a.wm1_e = a.wm1_i = 0.f;
+    } else if (resid) {
+      a.wm0_e = a.wm1_e = c->mu_e * sc;
+      a.wm0_i = a.wm1_i = c->mu_i * sc;
+    } else {
+      a.wm0_e = a.wm0_i = 0.f;
+      a.wm1_e = a.wm1_i = sc;
+    }
+  }
   a.fx_inv = std::ldexp(1.0, -c->fx_shift);
   a.grid_per_xcd = c->grid_per_xcd;
   a.V = c->V;
@@ -360,7 +387,7 @@ SliceArgs base_args(sd_ctx* c) {
   a.rb = c->rb;
   a.rb_hi = c->rb_hi;
   a.write_list = open_loop(g) ? 0 : 1;
-  a.out_cap = c->out_cap;
+  a.out_cap = c->list_cap;
   a.rec = c->rec_cap > 0 ? c->rec : nullptr;
   a.rec_n = c->counters + 3;
   a.rec_cap = c->rec_cap;
@@ -401,8 +428,9 @@ void decode_record(const sd_config& g, const uint8_t* rec, const uint8_t* dl, ui
   std::memcpy(&d, &u, 4);
   *w = g.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
   if (g.wform == SD_W_BF16_PACKED) {
-    *tgt = (int32_t)((int64_t)b * B + ((r >> 16) & ((1u << kPackOffBits) - 1)));
-    *dly = (uint8_t)(g.d_min + (int)(r >> (16 + kPackOffBits)));
+    const uint32_t slot = r >> 16;  // (delay - d_min) * B + offset
+    *tgt = (int32_t)((int64_t)b * B + (int32_t)(slot % (uint32_t)B));
+    *dly = (uint8_t)(g.d_min + (int)(slot / (uint32_t)B));
   } else {
     *tgt = (int32_t)((int64_t)b * B + (r >> 16));
     *dly = dl[e];
@@ -417,15 +445,13 @@ sd_status set_pending_input(sd_ctx* c, SliceArgs& a) {
     if (!c->in_list || c->pend_t0 < c->in_t0 || k >= c->in_slices)
       return fail(c, SD_ESTATE, "open-loop input not prepared for step %lld",
                   (long long)c->pend_t0);
-    a.n_regions = 1;
     a.in_list = c->in_list + c->in_off_h[k];
     a.in_cnt = c->in_cnt + k;
-    a.in_cap = 0;
+    a.in_cap = c->in_off_h[k + 1] - c->in_off_h[k];
   } else {
-    a.n_regions = c->NB;
     a.in_list = c->list[c->cur];
-    a.in_cnt = c->list_cnt[c->cur];
-    a.in_cap = c->out_cap;
+    a.in_cnt = c->cnt3 + c->ci;
+    a.in_cap = c->list_cap;
   }
   return SD_OK;
 }
@@ -469,7 +495,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->K = cfg->k_exc + cfg->k_inh;
   c->M = L.M;
   c->n_tiles = L.n_tiles;
-  c->out_cap = L.out_cap;
+  c->list_cap = L.list_cap;
   c->rec_cap = L.rec_cap;
   c->grid_per_xcd = (L.NB + 7) / 8;
   c->src_e_end = open_loop(*cfg) ? cfg->n_src_exc : cfg->n_exc;
@@ -489,6 +515,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   char* A = c->arena;
   c->row = (uint32_t*)(A + L.off_row);
   c->cursor = (uint32_t*)(A + L.off_cursor);
+  c->seg = (uint2*)(A + L.off_seg);
   c->tile_sums = (uint32_t*)(A + L.off_tiles);
   c->syn = A + L.off_syn;
   c->syn_dly = (uint8_t*)(A + L.off_dly);
@@ -499,8 +526,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->rb = (float*)(A + L.off_rb);
   c->list[0] = (uint32_t*)(A + L.off_list0);
   c->list[1] = (uint32_t*)(A + L.off_list1);
-  c->list_cnt[0] = (int32_t*)(A + L.off_cnt0);
-  c->list_cnt[1] = (int32_t*)(A + L.off_cnt1);
+  c->cnt3 = (int32_t*)(A + L.off_cnt);
   c->rec = (uint2*)(A + L.off_rec);
   c->wtab_e = A + L.off_wte;
   c->wtab_i = A + L.off_wti;
@@ -563,8 +589,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
                             c->stream));
   HIP_TRY(c, hipMemsetAsync(c->counters, 0, 8 * 8, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->overflow, 0, 4, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->list_cnt[0], 0, (size_t)c->NB * 4, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->list_cnt[1], 0, (size_t)c->NB * 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->cnt3, 0, 3 * 4, c->stream));
   HIP_TRY(c, launch_propagators(c->stream, g.model, g.h, g.tau_m, g.tau_syn, g.c_m, g.i_e,
                                 c->prop64, c->prop32));
   HIP_TRY(c, launch_init_state(c->stream, c->N, g.seed, g.v0_lo, g.v0_hi, c->V, c->y1, c->y2,
@@ -572,7 +597,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max, c->NB) + 64;
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max) + 64;
   if ((size_t)lds_max < lds)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
@@ -616,6 +641,7 @@ sd_status sd_build_connections(sd_ctx* c) {
   a.seed = g.seed;
   a.row = c->row;
   a.cursor = c->cursor;
+  a.seg = c->seg;
   a.syn = c->syn;
   a.syn_dly = c->syn_dly;
   a.wform = g.wform;
@@ -639,6 +665,7 @@ sd_status sd_build_connections(sd_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->cursor, c->row, (size_t)c->M * 4, hipMemcpyDeviceToDevice,
                             c->stream));
   if (c->K > 0) HIP_TRY(c, launch_fill(c->stream, a));
+  HIP_TRY(c, launch_seg_pairs(c->stream, a));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   uint32_t total = 0;
   HIP_TRY(c, hipMemcpy(&total, c->row + c->M - 1, 4, hipMemcpyDeviceToHost));
@@ -677,16 +704,19 @@ sd_status sd_update_neurons(sd_ctx* c, int32_t n_steps) {
                 (long long)c->pend_t0);
   SliceArgs a = base_args(c);
   if (fresh) {
+    // a new list: its counter (the one after the last) is zero; the one
+    // before it is cleared for the slice after this one
     c->cur ^= 1;
+    c->ci = (c->ci + 1) % 3;
     c->pend_t0 = c->t_now;
+    a.zero_cnt = c->cnt3 + (c->ci + 1) % 3;
   }
   a.do_deliver = 0;
   a.n_upd = n_steps;
   a.t_upd = c->t_now;
   a.t_slice0 = c->pend_t0;
   a.out_list = c->list[c->cur];
-  a.out_cnt = c->list_cnt[c->cur];
-  a.append = fresh ? 0 : 1;
+  a.out_cnt = c->cnt3 + c->ci;
   sd_status s = launch_slice_checked(c, a);
   if (s != SD_OK) return s;
   c->pend_open = true;
@@ -755,10 +785,9 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
       HIP_TRY(c, hipMemcpyAsync(packed, hs.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
       HIP_TRY(c, hipMemcpyAsync(d_n, &nn, 4, hipMemcpyHostToDevice, c->stream));
     }
-    a.n_regions = 1;
     a.in_list = packed;
     a.in_cnt = d_n;
-    a.in_cap = 0;
+    a.in_cap = n;
     if (n == 0) a.do_deliver = 0;
   }
   const int64_t w_lo = t0 + g.d_min;
@@ -814,13 +843,15 @@ sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
     a.t_upd = c->t_now;
     a.t_slice0 = c->t_now;
     const int nxt = c->cur ^ 1;
+    const int cn = (c->ci + 1) % 3;
     a.out_list = c->list[nxt];
-    a.out_cnt = c->list_cnt[nxt];
-    a.append = 0;
+    a.out_cnt = c->cnt3 + cn;
+    a.zero_cnt = c->cnt3 + (cn + 1) % 3;
     sd_status s = launch_slice_checked(c, a);
     if (s != SD_OK) return s;
     if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
     c->cur = nxt;
+    c->ci = cn;
     c->pend_open = true;
     c->pend_t0 = c->t_now;
     c->t_now += m;
@@ -965,14 +996,13 @@ sd_status sd_get_pending(sd_ctx* c, uint32_t* h_src, uint8_t* h_lag, int64_t cap
   if (slice_t0) *slice_t0 = c->pend_open ? c->pend_t0 : -1;
   if (!c->pend_open || open_loop(c->cfg)) return SD_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<int32_t> cnt((size_t)c->NB);
-  HIP_TRY(c, hipMemcpy(cnt.data(), c->list_cnt[c->cur], (size_t)c->NB * 4, hipMemcpyDeviceToHost));
-  std::vector<uint32_t> buf((size_t)c->NB * c->out_cap);
-  HIP_TRY(c, hipMemcpy(buf.data(), c->list[c->cur], buf.size() * 4, hipMemcpyDeviceToHost));
-  // gather, then order by (lag, src)
-  std::vector<uint32_t> all;
-  for (int32_t b = 0; b < c->NB; ++b)
-    for (int32_t i = 0; i < cnt[b]; ++i) all.push_back(buf[(size_t)b * c->out_cap + i]);
+  int32_t cnt = 0;
+  HIP_TRY(c, hipMemcpy(&cnt, c->cnt3 + c->ci, 4, hipMemcpyDeviceToHost));
+  const int64_t nl = std::min<int64_t>(cnt, c->list_cap);
+  std::vector<uint32_t> all((size_t)nl);
+  if (nl > 0)
+    HIP_TRY(c, hipMemcpy(all.data(), c->list[c->cur], (size_t)nl * 4, hipMemcpyDeviceToHost));
+  // blocks append in any order: sort by (lag, src)
   std::sort(all.begin(), all.end(), [](uint32_t x, uint32_t y) {
     const uint32_t lx = x & 31u, ly = y & 31u;
     return lx != ly ? lx < ly : (x >> 5) < (y >> 5);

@@ -23,33 +23,32 @@ constexpr int kFillChunk = 2048;     // draws ranked per build iteration
 //   WF_BF16        u32: low half BF16 weight, high half u16 offset in block
 //   WF_BF16_RESID  u32: low half BF16 residual d (w = mu (1 + d)), high half
 //                  u16 offset in block
-//   WF_PACKED      u32: bits 0-15 BF16 residual, 16-26 offset in block,
-//                  27-31 delay - d_min (no delay array)
-constexpr int kPackOffBits = 11;
-constexpr int kPackDlyBits = 5;
+//   WF_PACKED      u32: low half BF16 residual, high half the ring-window
+//                  slot (delay - d_min) * B + offset in block (no delay array)
 
 // Everything a slice launch needs (passed by value).
 struct SliceArgs {
   // network layout
-  const uint32_t* row;     // [NB * n_src + 1] segment pointers, block-major
+  const uint2* seg;        // [n_src][NB]: (first synapse, count) of source s in block b
   int64_t n_src;           // source ids
   const void* syn;         // synapse records (layout per weight form)
   const uint8_t* syn_dly;  // u8 delay in steps (not used by the packed form)
   int64_t N;               // local neurons
   int32_t NB, B;           // blocks, neurons per block
+  int32_t K;               // in-degree: block b's synapses start at b * B * K
   int32_t Dmin, Dmax, L;
   int64_t src_e_end;       // source ids below this are excitatory
-  float mu_e, mu_i;        // population means of the residual form
-  int32_t count_mode;      // deliver 1.0 per synapse
-  float fx_scale;          // 2^s: weights enter the LDS window as round(w * 2^s)
+  // fixed-point weight of a synapse: trunc(m1 * x + m0) with x the decoded
+  // BF16 residual (residual forms) or the weight itself (FP32, BF16); the
+  // pairs hold the scale 2^s of the LDS window (count mode: m1 = 0, m0 = 2^s)
+  float wm0_e, wm1_e, wm0_i, wm1_i;
   double fx_inv;           // 2^-s
   int32_t grid_per_xcd;    // blocks handled by one XCD (ceil(NB / 8))
   // delivery
   int32_t do_deliver;
-  int32_t n_regions;       // spike-list regions to read
-  const uint32_t* in_list; // region r at in_list + r * in_cap
-  const int32_t* in_cnt;   // entries per region (device)
-  int32_t in_cap;
+  const uint32_t* in_list; // spike entries (src << 5 | lag), contiguous
+  const int32_t* in_cnt;   // number of entries (device)
+  int64_t in_cap;          // entries the list can hold
   int64_t w_lo;            // first step of the delivery window
   // update
   int32_t n_upd;           // steps to update (0: none)
@@ -71,10 +70,10 @@ struct SliceArgs {
   int64_t rb_hi;           // rows of steps in [., rb_hi) hold valid sums
   // new spikes
   int32_t write_list;      // closed loop: feed spikes back
-  uint32_t* out_list;      // region b at out_list + b * out_cap
-  int32_t* out_cnt;
-  int32_t out_cap;
-  int32_t append;          // continue the region's existing entries
+  uint32_t* out_list;      // contiguous list of out_cap entries
+  int32_t* out_cnt;        // entries reserved so far (atomic; zero at a new slice)
+  int64_t out_cap;
+  int32_t* zero_cnt;       // list counter to clear for a later slice (may be null)
   uint2* rec;              // raster (step, id); null: off
   unsigned long long* rec_n;
   int64_t rec_cap;
@@ -91,8 +90,9 @@ struct BuildArgs {
   int64_t src_e_n, src_i_n, src_i_base;
   int32_t d_lo, n_dly;
   uint64_t seed;
-  uint32_t* row;           // counts, then exclusive scan
+  uint32_t* row;           // counts, then exclusive scan (block-major)
   uint32_t* cursor;        // fill cursors (copy of row)
+  uint2* seg;              // source-major (start, count) pairs
   void* syn;
   uint8_t* syn_dly;
   int32_t wform;
@@ -113,8 +113,9 @@ hipError_t launch_count(hipStream_t s, const BuildArgs& a);
 hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_sums,
                        int64_t n_tiles_cap);
 hipError_t launch_fill(hipStream_t s, const BuildArgs& a);
+hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a);
 hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform);
-size_t slice_lds_bytes(int B, int Dmin, int Dmax, int n_regions);
+size_t slice_lds_bytes(int B, int Dmin, int Dmax);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);
 hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,

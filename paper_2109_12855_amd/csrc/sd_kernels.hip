@@ -7,8 +7,9 @@
 //   window (d_max rows x B neurons), then advances its neurons through the
 //   next slice with the exact propagators (Sec. 2.1), reading inputs straight
 //   from the LDS window, and finally compacts the new spikes with a bitmask +
-//   block scan into the block's list, ordered (lag, neuron).  Rows of the
-//   window that are due in later slices are written to the ring in HBM.
+//   block scan and appends them, ordered (lag, neuron) within the block, to
+//   the slice's contiguous spike list.  Rows of the window that are due in
+//   later slices are written to the ring in HBM.
 //
 // Build (once, untimed, Sec. 2.2):
 //   k_count / scan / k_fill lay out the block-major table: the synapses into
@@ -17,6 +18,8 @@
 //   workgroup therefore only ever reads its own block's region, which keeps
 //   its address translations local.  k_fill ranks equal sources inside each
 //   chunk of draws with an LDS bitonic sort, so the layout is deterministic.
+//   k_seg_pairs then stores the segment pointers source-major, as (start,
+//   count) pairs: the blocks resolving one spike read neighbouring words.
 #include <hip/hip_runtime.h>
 
 #include "sd_internal.h"
@@ -283,7 +286,8 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
         if (a.fixed) wb = inh ? a.fix_bits_i : a.fix_bits_e;
         else wb = inh ? ((const uint16_t*)a.wtab_i)[widx] : ((const uint16_t*)a.wtab_e)[widx];
         uint32_t rec = (wb & 0xffffu) | ((uint32_t)jl << 16);
-        if (a.wform == WF_PACKED) rec |= (uint32_t)(dly - a.d_min) << (16 + kPackOffBits);
+        if (a.wform == WF_PACKED)
+          rec = (wb & 0xffffu) | ((uint32_t)((int64_t)(dly - a.d_min) * a.B + jl) << 16);
         ((uint32_t*)a.syn)[pos] = rec;
       }
       if (a.wform != WF_PACKED) a.syn_dly[pos] = (uint8_t)dly;
@@ -302,52 +306,90 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
   }
 }
 
+// Source-major segment pointers: seg[s * NB + b] = (start, count) of the
+// synapses from s into block b, from the block-major scan.
+__global__ void k_seg_pairs(const uint32_t* row, int64_t n_src, int32_t NB, uint2* seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_src * NB) return;
+  const int64_t s = i / NB;
+  const int64_t b = i - s * NB;
+  const uint32_t lo = row[b * n_src + s];
+  seg[i] = make_uint2(lo, row[b * n_src + s + 1] - lo);
+}
+
 // ---------------------------------------------------------------------------
 // the fused slice kernel
 // ---------------------------------------------------------------------------
-// Synapse base + i (base wave-uniform): offset in the block, delay - d_min
-// and the decoded FP32 weight.
+// Raw synapse record as loaded (decoded only when its add is issued, so a
+// wave keeps one to three registers per segment in flight).
+template <int WF> struct SynRaw;
+template <> struct SynRaw<WF_FP32> { uint64_t r; uint32_t d; };
+template <> struct SynRaw<WF_BF16> { uint32_t r; uint32_t d; };
+template <> struct SynRaw<WF_BF16_RESID> { uint32_t r; uint32_t d; };
+template <> struct SynRaw<WF_PACKED> { uint32_t r; };
+
+// segment loads in flight per wave (register budget of the record form)
+template <int WF> struct SynGroup { static constexpr int n = 20; };
+template <> struct SynGroup<WF_FP32> { static constexpr int n = 16; };
+template <> struct SynGroup<WF_PACKED> { static constexpr int n = 32; };
+constexpr int kMaxGroup = 32;
+
+// A record through buffer resources over one block's records and delays:
+// element index i, or kOobIndex for a lane or slot with nothing to load:
+// blocks hold at most 2^28 synapses and 2^30 record bytes (checked at
+// creation), so that offset is out of range and the load returns zero
+// without reading memory.
+constexpr uint32_t kOobIndex = 1u << 28;
+constexpr int kBufWord3 = 0x00020000;  // gfx9 buffer resource: 32-bit dword format
+
 template <int WF>
-__device__ __forceinline__ void syn_load(const void* syn, const uint8_t* dly, uint32_t base, int i,
-                                         int32_t j0, int Dmin, float mu, int& off, int& dd,
-                                         float& w) {
+__device__ __forceinline__ SynRaw<WF> syn_fetch_buf(__amdgpu_buffer_rsrc_t rs,
+                                                    __amdgpu_buffer_rsrc_t rd, uint32_t i) {
+  SynRaw<WF> x;
   if constexpr (WF == WF_FP32) {
-    const uint64_t r = ((const uint64_t*)syn + base)[i];
-    w = __uint_as_float((uint32_t)r);
-    off = (int)(r >> 32) - j0;
-    dd = (int)(dly + base)[i] - Dmin;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(i * 8u), 0, 0);
+    x.r = ((uint64_t)v[1] << 32) | (uint32_t)v[0];
+    x.d = __builtin_amdgcn_raw_buffer_load_b8(rd, (int)i, 0, 0);
   } else if constexpr (WF == WF_PACKED) {
-    const uint32_t r = ((const uint32_t*)syn + base)[i];
-    const float d = __uint_as_float(r << 16);
-    w = fmaf(mu, d, mu);
-    off = (int)((r >> 16) & ((1u << kPackOffBits) - 1));
-    dd = (int)(r >> (16 + kPackOffBits));
+    x.r = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0);
   } else {
-    const uint32_t r = ((const uint32_t*)syn + base)[i];
-    const float d = __uint_as_float(r << 16);
-    w = (WF == WF_BF16) ? d : fmaf(mu, d, mu);
-    off = (int)(r >> 16);
-    dd = (int)(dly + base)[i] - Dmin;
+    x.r = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0);
+    x.d = __builtin_amdgcn_raw_buffer_load_b8(rd, (int)i, 0, 0);
   }
+  return x;
 }
 
-
-// Fixed-point quantum of the LDS ring window: a weight w enters as the
-// integer round(w * 2^s); sums are exact 64-bit integers (LDS integer
-// atomics are ~10x faster than float atomics on gfx950, and the result no
-// longer depends on the order of the adds).
-__device__ __forceinline__ long long to_fixed(float w, float scale) {
-  return (long long)__float2int_rn(w * scale);
+// Window slot ((delay - d_min) * B + offset in block) and fixed-point weight
+// trunc(m1 * x + m0) of a record, x its BF16 residual or its weight.  With
+// the window quantum chosen so that max|w| * 2^s <= 2^30, w * 2^s is exact
+// in FP32 for |w| * 2^s >= 2^23, so the truncation only rounds weights
+// below 2^-7 of the largest.
+template <int WF>
+__device__ __forceinline__ void syn_decode(const SynRaw<WF>& x, int32_t j0, int Dmin, int B,
+                                           float m0, float m1, int& slot, int& v) {
+  float w;
+  if constexpr (WF == WF_FP32) {
+    w = __uint_as_float((uint32_t)x.r);
+    slot = ((int)x.d - Dmin) * B + ((int)(x.r >> 32) - j0);
+  } else if constexpr (WF == WF_PACKED) {
+    w = __uint_as_float(x.r << 16);
+    slot = (int)(x.r >> 16);
+  } else {
+    w = __uint_as_float(x.r << 16);
+    slot = ((int)x.d - Dmin) * B + (int)(x.r >> 16);
+  }
+  v = (int)fmaf(m1, w, m0);  // conversion truncates toward zero
 }
+
 __device__ __forceinline__ float from_fixed(long long q, double inv) {
   return (float)((double)q * inv);
 }
 
 // LDS layout of a slice workgroup (byte offsets, 16-byte aligned pieces)
 struct SliceLds {
-  size_t win, carry, dcnt, mask, thr, pre, scr, desc, total;
+  size_t win, carry, dcnt, mask, thr, scr, desc, meta, total;
 };
-__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax, int n_regions) {
+__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   SliceLds L;
   size_t o = 0;
@@ -356,18 +398,16 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax, 
   L.dcnt = o;  o = up(o + (size_t)Dmin * B);            // Poisson-drive counts (u8)
   L.mask = o;  o = up(o + (size_t)Dmin * (B / 32) * 4); // spike bitmask
   L.thr = o;   o = up(o + (size_t)kMaxThr * 4);         // drive thresholds
-  L.pre = o;   o = up(o + (size_t)(n_regions + 1) * 4); // spike-list region prefix
-  L.scr = o;   o = up(o + (size_t)(kSliceThreads / 64 + 1) * 4);
-  L.desc = o;  o = up(o + (size_t)kSliceThreads * 16);   // per-wave spike descriptors
+  L.scr = o;   o = up(o + (size_t)(kSliceThreads / 64 + 2) * 4);
+  // one descriptor per spike of a chunk, plus one group of padding so a
+  // wave's last group reads in bounds without clamping its index
+  L.desc = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 8);  // (start in block, count)
+  L.meta = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 4);  // lag row, count, population
   L.total = o;
   return L;
 }
 
-size_t slice_lds_bytes(int B, int Dmin, int Dmax, int n_regions) {
-  return slice_lds_layout(B, Dmin, Dmax, n_regions).total;
-}
-
-constexpr int kUnroll = 16;
+size_t slice_lds_bytes(int B, int Dmin, int Dmax) { return slice_lds_layout(B, Dmin, Dmax).total; }
 
 template <int WF>
 __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
@@ -387,29 +427,37 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   const int Wd = B >> 5;
   const int Dmin = a.Dmin;
 
-  const SliceLds Lo = slice_lds_layout(B, Dmin, a.Dmax, a.n_regions);
+  const SliceLds Lo = slice_lds_layout(B, Dmin, a.Dmax);
   long long* win = (long long*)(lds_raw + Lo.win);
   float* carry = (float*)(lds_raw + Lo.carry);
   uint8_t* dcnt = lds_raw + Lo.dcnt;
   uint32_t* mask = (uint32_t*)(lds_raw + Lo.mask);
   uint32_t* thr = (uint32_t*)(lds_raw + Lo.thr);
-  int32_t* pre = (int32_t*)(lds_raw + Lo.pre);
   int32_t* scr = (int32_t*)(lds_raw + Lo.scr);
-  // descriptor of spike s0 + u of this wave's batch: {segment start, length,
-  // lag, population mean weight}, read back by all lanes as an LDS broadcast
-  uint4* desc = (uint4*)(lds_raw + Lo.desc) + wv * 64;
+  // spike c0 + i of the current chunk: its segment in this block (start
+  // relative to the block's first synapse, count) and its meta word
+  // lag * B << 7 | min(count, 65) | excitatory 0 / inhibitory 1 << 31, read
+  // back by whole waves as LDS broadcasts
+  uint2* desc = (uint2*)(lds_raw + Lo.desc);
+  uint32_t* meta = (uint32_t*)(lds_raw + Lo.meta);
+
+  // loads whose latency the LDS zeroing below covers
+  const uint32_t thr_v = (tid < kMaxThr && tid < a.n_thr) ? a.thr[tid] : 0xffffffffu;
+  int64_t total = a.do_deliver ? (int64_t)*a.in_cnt : 0;
+  if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
 
   // window rows cover steps [w_lo, w_lo + Dmax)
   const int64_t w_lo = a.w_lo;
   if (a.do_deliver)
     for (int i = tid; i < a.Dmax * B; i += kSliceThreads) win[i] = 0;
   for (int i = tid; i < Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
-  if (tid < kMaxThr) thr[tid] = tid < a.n_thr ? a.thr[tid] : 0xffffffffu;
   // events of this block, summed in LDS: one global atomic per workgroup
   // (thousands of same-address global atomics per launch back up the
   // memory queues of every compute unit)
   __shared__ unsigned long long s_ev;
   if (tid == 0) s_ev = 0;
+  // the list counter of a later slice starts at zero
+  if (b == 0 && tid == 0 && a.zero_cnt) *a.zero_cnt = 0;
 
   // ---- prologue: issue the loads the update will need -------------------
   // Carried ring rows (deliveries of earlier slices) and this thread's
@@ -478,117 +526,122 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   int rounds_done = 0;
 
   // ---- deliver the completed slice into the LDS window (Alg. REF) -------
+  if (tid < kMaxThr) thr[tid] = thr_v;
   if (a.do_deliver) {
-    const int R = a.n_regions;
-    const int per = (R + kSliceThreads - 1) / kSliceThreads;
-    int s = 0;
-    for (int q = 0; q < per; ++q) {
-      const int r = tid * per + q;
-      if (r < R) s += a.in_cnt[r];
-    }
-    int tot;
-    int ex = block_excl_scan<int>(s, scr, tot);  // also orders thr / zeroing
-    for (int q = 0; q < per; ++q) {
-      const int r = tid * per + q;
-      if (r < R) {
-        pre[r] = ex;
-        ex += a.in_cnt[r];
-      }
-    }
-    if (tid == 0) pre[R] = tot;
-    __syncthreads();
-    const int64_t total = tot;
-    const float fx = a.count_mode ? 0.f : a.fx_scale;
-    const long long one_q = (long long)a.fx_scale;  // count mode: 1.0 per synapse
+    __syncthreads();  // thr / zeroing visible
 
-    // Every wave takes an equal contiguous share of the spikes.  Each block
-    // starts at a different point of the list (the sums are exact integers,
-    // so the order is free): otherwise all blocks would read the same
-    // relative offsets of their equally sized regions at the same moment.
+    // Spikes are taken in chunks of one per thread.  Each block starts at a
+    // different point of the list (the sums are exact integers, so the order
+    // is free): otherwise all blocks would read the same relative offsets of
+    // their equally sized regions at the same moment.
     const int64_t rot = total > 0 ? ((int64_t)b * 7919) % total : 0;
-    const int64_t per_w = (total + nwv - 1) / nwv;
-    const int64_t w_beg = (int64_t)wv * per_w;
-    const int64_t w_end = (w_beg + per_w) < total ? (w_beg + per_w) : total;
+    constexpr int G = SynGroup<WF>::n;
+    __shared__ int s_next;  // next unclaimed spike of the chunk
+    // this block's synapses: [j0 * K, (j0 + nb) * K) (fixed in-degree)
+    const uint32_t reg_lo = (uint32_t)(j0 * a.K);
+    const uint32_t reg_n = (uint32_t)((int64_t)nb * a.K);
+    constexpr uint32_t rec_bytes = (WF == WF_FP32) ? 8u : 4u;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)a.syn + (size_t)reg_lo * rec_bytes), 0,
+        (int)(reg_n * rec_bytes), kBufWord3);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.syn_dly ? a.syn_dly + reg_lo : nullptr), 0, (int)reg_n, kBufWord3);
     uint64_t ev = 0;
-    for (int64_t base = w_beg; base < w_end; base += 64) {
-      const int64_t i = base + lane;
-      uint32_t lo = 0;
-      int len = 0, lag = 0;
-      float mu = 0.f;
-      if (i < w_end) {
+    for (int64_t c0 = 0; c0 < total; c0 += kSliceThreads) {
+      const int n_c = (int)((total - c0) < kSliceThreads ? (total - c0) : kSliceThreads);
+      // (1) every thread resolves one spike into its segment of this block:
+      // the list entry, then the segment's (start, count) pair
+      if (tid < n_c) {
+        const int64_t i = c0 + tid;
         const int64_t ir = (i + rot) < total ? i + rot : i + rot - total;
-        int rlo = 0, rhi = R;
-        while (rhi - rlo > 1) {
-          const int m = (rlo + rhi) >> 1;
-          if (pre[m] <= ir) rlo = m;
-          else rhi = m;
-        }
-        const uint32_t ent = a.in_list[(int64_t)rlo * a.in_cap + (ir - pre[rlo])];
+        const uint32_t ent = a.in_list[ir];
         const uint32_t src = ent >> 5;
-        lag = (int)(ent & 31u);
-        if (lag < Dmin) {
-          const int64_t p = (int64_t)b * a.n_src + src;
-          lo = a.row[p];
-          len = (int)(a.row[p + 1] - lo);
-          mu = ((int64_t)src < a.src_e_end) ? a.mu_e : a.mu_i;
-        } else {
-          atomicOr(a.overflow, 4);
-        }
+        const int lag = (int)(ent & 31u);
+        uint2 sg = make_uint2(reg_lo, 0u);
+        if (lag < Dmin && (int64_t)src < a.n_src) sg = a.seg[(int64_t)src * a.NB + b];
+        else atomicOr(a.overflow, 4);
+        const uint32_t len = sg.y;
+        ev += (uint64_t)len;
+        desc[tid] = make_uint2(sg.x - reg_lo, len);
+        meta[tid] = ((uint32_t)(lag * B) << 7) | (len < 65u ? len : 65u) |
+                    (((int64_t)src >= a.src_e_end) ? 0x80000000u : 0u);
       }
-      ev += (uint64_t)len;
-      desc[lane] = make_uint4(lo, (uint32_t)len, (uint32_t)lag, __float_as_uint(mu));
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int n_here = (int)((w_end - base) < 64 ? (w_end - base) : 64);
-      for (int s0 = 0; s0 < n_here; s0 += kUnroll) {
-        // Branch-free loads: lanes past a segment's end re-read its last
-        // element (an empty segment reads element 0), so all kUnroll segment
-        // loads issue back to back; only the LDS adds are predicated.
-        int off[kUnroll], dl[kUnroll];
-        float w[kUnroll];
+      if (tid == 0) s_next = 0;
+      __syncthreads();
+      // (2) waves take groups of G spikes from a shared counter until the
+      // chunk is done (a wave slowed by issue priority or memory latency
+      // simply takes fewer groups).  G loads issue back to back (lanes past
+      // a segment's end and slots past the chunk load nothing: their buffer
+      // offset is out of range), then the adds; the group bound is uniform.
+      for (;;) {
+        int g0 = 0;
+        if (lane == 0)
+          g0 = __hip_atomic_fetch_add(&s_next, G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        g0 = __builtin_amdgcn_readfirstlane(g0);
+        if (g0 >= n_c) break;
+        const int n_here = (n_c - g0) < G ? (n_c - g0) : G;
+        SynRaw<WF> raw[G];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const uint4 d = desc[s0 + u];
-          const int sl = (int)d.y;
-          const int li = lane < sl ? lane : (sl > 0 ? sl - 1 : 0);
-          const uint32_t sb = sl > 0 ? d.x : 0u;
-          syn_load<WF>(a.syn, a.syn_dly, sb, li, (int32_t)j0, Dmin, __uint_as_float(d.w), off[u],
-                       dl[u], w[u]);
+        for (int u = 0; u < G; ++u) {
+          const uint2 d = desc[g0 + u];  // past the share: stale or padding, masked
+          // the start also enters the predicate, so both halves are read
+          // unconditionally (no per-slot branch around the LDS read)
+          const bool on = (u < n_here) & (lane < (int)d.y) & (d.x != 0xffffffffu);
+          raw[u] = syn_fetch_buf<WF>(rs, rd, on ? d.x + (uint32_t)lane : kOobIndex);
         }
         // ALU work while the loads are in flight
         if (rounds_done < n_rounds) drive_round(rounds_done++);
+        uint32_t mt[G];
+        bool any_long = false;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const uint4 d = desc[s0 + u];
-          if (lane < (int)d.y) {
-            const long long v = a.count_mode ? one_q : to_fixed(w[u], fx);
-            __hip_atomic_fetch_add((unsigned long long*)&win[((int)d.z + dl[u]) * B + off[u]],
-                                   (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int u = 0; u < G; ++u) {
+          mt[u] = meta[g0 + u];
+          any_long |= (mt[u] & 127u) > 64u;  // unconditional use: no sinking
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          // the meta word is uniform: population constants and the lag row
+          // come out of scalar registers
+          const uint32_t m = __builtin_amdgcn_readfirstlane(mt[u]);
+          const uint32_t sel = (uint32_t)((int32_t)m >> 31);  // all ones: inhibitory
+          const float m0 = __uint_as_float((__float_as_uint(a.wm0_e) & ~sel) |
+                                           (__float_as_uint(a.wm0_i) & sel));
+          const float m1 = __uint_as_float((__float_as_uint(a.wm1_e) & ~sel) |
+                                           (__float_as_uint(a.wm1_i) & sel));
+          long long* row = win + ((m >> 7) & 0xffffffu);
+          if ((u < n_here) & (lane < (int)(m & 127u))) {
+            int slot, v;
+            syn_decode<WF>(raw[u], (int32_t)j0, Dmin, B, m0, m1, slot, v);
+            __hip_atomic_fetch_add((unsigned long long*)&row[slot], (unsigned long long)(long long)v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
-        // segments longer than one wave
-        for (int u = 0; u < kUnroll; ++u) {
-          const uint4 d = desc[s0 + u];
-          for (int e0 = 64; e0 < (int)d.y; e0 += 64) {
-            if (lane + e0 < (int)d.y) {
-              int o, dd;
-              float wl;
-              syn_load<WF>(a.syn, a.syn_dly, d.x, e0 + lane, (int32_t)j0, Dmin,
-                           __uint_as_float(d.w), o, dd, wl);
-              const long long v = a.count_mode ? one_q : to_fixed(wl, fx);
-              __hip_atomic_fetch_add((unsigned long long*)&win[((int)d.z + dd) * B + o],
-                                     (unsigned long long)v, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+        // segments longer than one wave (rare: a block's share of a source's
+        // targets is ~K/NB)
+        if (__builtin_amdgcn_readfirstlane((int)any_long)) {
+          for (int u = 0; u < n_here; ++u) {
+            const uint2 d = desc[g0 + u];
+            const uint32_t m = meta[g0 + u];
+            const int sl = __builtin_amdgcn_readfirstlane((int)d.y);
+            const bool inh = (int)m < 0;
+            for (int e0 = 64; e0 < sl; e0 += 64) {
+              const bool on = lane + e0 < sl;
+              const SynRaw<WF> x =
+                  syn_fetch_buf<WF>(rs, rd, on ? d.x + (uint32_t)(e0 + lane) : kOobIndex);
+              if (on) {
+                int slot, v;
+                syn_decode<WF>(x, (int32_t)j0, Dmin, B, inh ? a.wm0_i : a.wm0_e,
+                               inh ? a.wm1_i : a.wm1_e, slot, v);
+                __hip_atomic_fetch_add(
+                    (unsigned long long*)&win[(int)((m >> 7) & 0xffffffu) + slot],
+                    (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
             }
           }
         }
       }
-      // the next batch overwrites the descriptors
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __syncthreads();  // the next chunk overwrites the descriptors
     }
     // events of this wave
 #pragma unroll
@@ -596,6 +649,7 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     if (lane == 0 && ev)
       __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
   } else {
     __syncthreads();  // thr / zeroing visible
   }
@@ -624,10 +678,7 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
     }
   }
   __syncthreads();
-  if (tid == 0 && a.do_deliver) {
-    if (s_ev) atomicAdd(a.ev_count, s_ev);
-    if (b == 0) atomicAdd(a.spk_in_count, (unsigned long long)pre[a.n_regions]);
-  }
+  if (tid == 0 && a.do_deliver && s_ev) atomicAdd(a.ev_count, s_ev);
 
   // ---- update the next slice's steps (exact propagation, Sec. 2.1) -------
   if (a.n_upd > 0) {
@@ -723,11 +774,12 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   }
   __syncthreads();
 
-  // ---- compaction: (lag, neuron)-ordered spike list of this block -------
+  // ---- compaction: this block's new spikes, (lag, neuron) ordered --------
   if (a.n_upd > 0) {
     const int lag0 = (int)(a.t_upd - a.t_slice0);
     const int nq = a.n_upd * Wd;
-    const int base = a.append ? a.out_cnt[b] : 0;
+    __shared__ int s_base;
+    __shared__ unsigned long long s_rbase;
     int running = 0;
     for (int q0 = 0; q0 < nq; q0 += kSliceThreads) {
       const int q = q0 + tid;
@@ -735,15 +787,16 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
       int tot;
       const int ex = block_excl_scan<int>(__popc(m), scr, tot);
       if (tot == 0) continue;
-      unsigned long long rbase = 0;
-      if (a.rec) {
-        __shared__ unsigned long long s_rbase;
-        if (tid == 0) s_rbase = atomicAdd(a.rec_n, (unsigned long long)tot);
-        __syncthreads();
-        rbase = s_rbase;
-        __syncthreads();
+      // one reservation per block in the slice's list (and the raster)
+      if (tid == 0) {
+        s_base = a.write_list ? atomicAdd(a.out_cnt, tot) : 0;
+        s_rbase = a.rec ? atomicAdd(a.rec_n, (unsigned long long)tot) : 0ull;
       }
-      int pos = running + ex;
+      __syncthreads();
+      const int64_t base = s_base;
+      const unsigned long long rbase = s_rbase;
+      __syncthreads();
+      int pos = ex;
       const int lg = lag0 + q / Wd;
       const int nbase = (q % Wd) * 32;
       while (m) {
@@ -752,12 +805,12 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
         const int64_t gn = j0 + nbase + bit;
         if (a.write_list) {
           if (base + pos < a.out_cap)
-            a.out_list[(int64_t)b * a.out_cap + base + pos] = ((uint32_t)gn << 5) | (uint32_t)lg;
+            a.out_list[base + pos] = ((uint32_t)gn << 5) | (uint32_t)lg;
           else
             atomicOr(a.overflow, 1);
         }
         if (a.rec) {
-          const unsigned long long rp = rbase + (unsigned long long)pos - running;
+          const unsigned long long rp = rbase + (unsigned long long)pos;
           if ((int64_t)rp < a.rec_cap) a.rec[rp] = make_uint2((uint32_t)(a.t_slice0 + lg), (uint32_t)gn);
           else atomicOr(a.overflow, 2);
         }
@@ -765,13 +818,7 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
       }
       running += tot;
     }
-    if (tid == 0) {
-      if (a.write_list) {
-        const int c = base + running;
-        a.out_cnt[b] = c < a.out_cap ? c : a.out_cap;
-      }
-      if (running) atomicAdd(a.spk_count, (unsigned long long)running);
-    }
+    if (tid == 0 && running) atomicAdd(a.spk_count, (unsigned long long)running);
   }
 }
 
@@ -871,8 +918,15 @@ hipError_t launch_fill(hipStream_t s, const BuildArgs& a) {
   return hipGetLastError();
 }
 
+hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a) {
+  const int64_t n = a.n_src * a.NB;
+  hipLaunchKernelGGL(k_seg_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.row, a.n_src,
+                     a.NB, a.seg);
+  return hipGetLastError();
+}
+
 hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform) {
-  const size_t lds = slice_lds_bytes(a.B, a.Dmin, a.Dmax, a.n_regions);
+  const size_t lds = slice_lds_bytes(a.B, a.Dmin, a.Dmax);
   const dim3 grid((unsigned)(8 * a.grid_per_xcd)), block(kSliceThreads);
   switch (wform) {
     case WF_FP32:
