@@ -14,8 +14,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +27,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_slice_alpha_112500_bf16_packed_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_12855_amd", "csrc", f)
+                  for f in ("sd_kernels.hip", "sd_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per slice launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when the summary is missing or
+    was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic_json: (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    t = json.loads(m.group(1))
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t
+
+
+def copy_probe():
+    """A plain elementwise copy (read and write COPY_PROBE_BYTES each): its
+    FETCH_SIZE / WRITE_SIZE counters calibrate the slice kernel's."""
+    import torch
+
+    n = COPY_PROBE_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    _log(f"copy probe: 3 x {COPY_PROBE_BYTES} B read + written")
 
 
 def _log(msg: str):
@@ -64,23 +111,11 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
     events = s1["events_delivered"] - s0["events_delivered"]
     spikes = s1["spikes_delivered"] - s0["spikes_delivered"]
     emitted = s1["spikes_emitted"] - s0["spikes_emitted"]
-    # per-launch durations: an event pair around each slice launch, on the
-    # stream the kernel runs on (torch's current stream is the context's)
-    k_ms = None
-    if per_launch:
-        n_l = min(steps, 200)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(n_l)]
-        s2 = net.stats()
-        for a, b in evs:
-            a.record()
-            net.simulate_steps(d_min)
-            b.record()
-        torch.cuda.synchronize()
-        s3 = net.stats()
-        k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-        ev_l = (s3["events_delivered"] - s2["events_delivered"]) / n_l
-        sp_l = (s3["spikes_delivered"] - s2["spikes_delivered"]) / n_l
+    launches = s1["slices"] - s0["slices"]
+    # Every timed step is one fused slice launch and nothing else runs on
+    # the stream (torch's current stream is the context's), so the events
+    # around the timed region give the kernel's average launch duration.
+    k_ms = ms / launches if per_launch and launches > 0 else None
     n = net.n_local
     b_syn = {0: 9, 1: 5, 2: 5, 3: 4}[cfg["wform"]]
     s_state = 16 if cfg["model"] == 1 else 8
@@ -92,8 +127,9 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
         alg_bytes_per_step=b_alg, alg_gbs=b_alg / (ms / steps * 1e-3) / 1e9,
     )
     if k_ms is not None:
-        b_l = algorithmic_bytes(ev_l, sp_l, n, d_min, b_syn, s_state)
-        out.update(kernel_ms=k_ms, kernel_alg_bytes=b_l, kernel_gbs=b_l / (k_ms * 1e-3) / 1e9)
+        b_l = algorithmic_bytes(events / launches, spikes / launches, n, d_min, b_syn, s_state)
+        out.update(kernel_ms=k_ms, launches=launches, kernel_alg_bytes=b_l,
+                   kernel_gbs=b_l / (k_ms * 1e-3) / 1e9)
     net.close()
     del net
     torch.cuda.empty_cache()
@@ -137,6 +173,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -159,6 +197,8 @@ def main():
         _log(f"form {f}")
         res[f] = run_form(forms[f], args.steps, args.warmup)
         _log(json.dumps(res[f]))
+    if args.copy_probe:
+        copy_probe()
     head_name = next((f for f in ("bf16_packed", "bf16_resid") if f in res), next(iter(res)))
     head = res[head_name]
     cpu = None
@@ -166,9 +206,11 @@ def main():
         cpu = cpu_baseline(dict(base, wform=0))
     roof = None
     if "kernel_ms" in head:
+        tr = measured_traffic() if head_name == "bf16_packed" else None
         roof = {"bound": "hbm", "achieved": round(head["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": None}
+                "traffic": (round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
+                            if tr else None)}
     line = {
         "metric": "synaptic events delivered/s",
         "value": head["events_per_s"],
