@@ -136,6 +136,38 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
     return out
 
 
+def ring_errors(base: dict, forms: list, n_spikes: int = 900, seed: int = 2021) -> dict:
+    """Ring contents of each BF16 storage form against the FP32 form after
+    delivering the same replay list (one slice's worth of spikes): normwise
+    relative error over all cells, and the largest cell error relative to
+    the largest FP32 cell."""
+    import torch
+
+    from paper_2109_12855_amd import sdeliver, workloads
+
+    n = base["n_exc"] + base["n_inh"]
+    src, lag = workloads.replay_spikes(n, n_spikes, base["d_min"], seed=seed)
+    d_src = torch.from_numpy(src.view(np.int32)).cuda()
+    d_lag = torch.from_numpy(lag).cuda()
+    rings = {}
+    for name, wf in [("fp32", 0)] + [(f, {"bf16": 1, "bf16_resid": 2, "bf16_packed": 3}[f])
+                                     for f in forms if f != "fp32"]:
+        net = sdeliver.Net(dict(base, wform=wf)).build()
+        net.deliver(d_src, d_lag, 0)
+        rings[name] = net.ring(base["ring_len"]).astype(np.float64)
+        net.close()
+        del net
+        torch.cuda.empty_cache()
+    ref = rings.pop("fp32")
+    norm = float(np.linalg.norm(ref))
+    out = {}
+    for name, r in rings.items():
+        d = r - ref
+        out[name] = {"normwise": float(np.linalg.norm(d) / norm),
+                     "max_cell_over_max_ref": float(np.abs(d).max() / np.abs(ref).max())}
+    return {"vs": "fp32 form", "spikes": int(len(src)), "forms": out}
+
+
 def cpu_baseline(cfg: dict, budget_s: float = 12.0, frac: int = 16) -> dict:
     """The FP64 oracle on the host: delivery + update of a 1/frac target
     sample of the same network, fed seeded synthetic spike lists at the
@@ -173,6 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16-vs-FP32 ring error report")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -199,6 +233,11 @@ def main():
         _log(json.dumps(res[f]))
     if args.copy_probe:
         copy_probe()
+    prec = None
+    if not args.no_precision:
+        prec = ring_errors(dict(base, name="precision"),
+                           [f for f in args.forms.split(",") if f != "fp32"])
+        _log("precision: " + json.dumps(prec))
     head_name = next((f for f in ("bf16_packed", "bf16_resid") if f in res), next(iter(res)))
     head = res[head_name]
     cpu = None
@@ -230,6 +269,7 @@ def main():
                    "parallelism": "single_gpu"},
         "achieved_alg_gbs": head["alg_gbs"],
         "forms": res,
+        "precision": prec,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -206,6 +206,33 @@ sd_status sd_get_tables(sd_ctx* ctx, float* h_we, float* h_wi, uint32_t* h_thr, 
 sd_status sd_host_tables(const sd_config* cfg, float* h_we, float* h_wi, uint32_t* h_thr,
                          int32_t* n_thr);
 
+/* --- batched networks ------------------------------------------------------
+ * Independent networks (a parameter sweep) advanced together.  Each member
+ * runs the simulation cycle of Sec. 1 / Sec. 2.1 exactly as a single
+ * context does; a slice of all members is one fused launch over the union
+ * of their target blocks, so small networks share the device instead of
+ * each leaving it mostly idle.  Members are ordinary contexts
+ * (sd_batch_member) for read-back; they must share model, weight form, h
+ * and d_min, be closed loop, and be advanced only through the batch.
+ * Results equal those of each member run alone (the same per-block code,
+ * exact integer window sums). */
+typedef struct sd_batch sd_batch;
+
+/* Create n members from cfgs[0..n) on the current device, all ordered on
+ * hip_stream; each context allocates its own device memory.  On failure
+ * *out still holds a batch for sd_batch_last_error / sd_batch_destroy. */
+sd_status sd_batch_create(const sd_config* cfgs, int32_t n, void* hip_stream, sd_batch** out);
+void sd_batch_destroy(sd_batch* b);
+const char* sd_batch_last_error(const sd_batch* b);
+int32_t sd_batch_size(const sd_batch* b);
+/* member i (borrowed; owned by the batch), or NULL */
+sd_ctx* sd_batch_member(sd_batch* b, int32_t i);
+/* sd_build_connections on every member */
+sd_status sd_batch_build(sd_batch* b);
+/* advance every member by n_steps (or round(t_ms / h) steps) */
+sd_status sd_batch_simulate_steps(sd_batch* b, int64_t n_steps);
+sd_status sd_batch_simulate(sd_batch* b, double t_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,95 @@ void quantile_weights(const sd_config& g, float* we, float* wi) {
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+namespace {
+
+// Per-slice kernel arguments live in device memory (the kernel then loads
+// fields where it uses them instead of holding the whole struct in scalar
+// registers).  They are uploaded in chunks through a pinned double buffer:
+// a chunk's copy and then its launches go onto the stream; the host reuses
+// a half of the staging buffer only after that half's copy has completed.
+struct SliceLauncher {
+  int per = 1;                  // argument structs per slice (member networks)
+  int cap = 0;                  // slices per chunk
+  sd::SliceArgs* d_args = nullptr;  // [2][cap][per]
+  sd::SliceArgs* h_args = nullptr;  // pinned staging, same shape
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pend[2] = {false, false};
+  int half = 0;
+  int2* d_map = nullptr;        // workgroup -> (network, block)
+  int32_t n_blocks = 0;
+  size_t lds = 0;
+  int wform = 0;
+};
+
+// XCD-aware workgroup map: entry list[i] goes to workgroup
+// (i % per_xcd) * 8 + i / per_xcd, so consecutive entries share an XCD.
+std::vector<int2> xcd_map(const std::vector<int2>& list) {
+  const int64_t T = (int64_t)list.size();
+  const int64_t per_xcd = (T + 7) / 8;
+  std::vector<int2> map((size_t)(8 * per_xcd), make_int2(-1, 0));
+  for (int64_t gx = 0; gx < 8 * per_xcd; ++gx) {
+    const int64_t i = (gx & 7) * per_xcd + (gx >> 3);
+    if (i < T) map[(size_t)gx] = list[(size_t)i];
+  }
+  return map;
+}
+
+hipError_t launcher_init(SliceLauncher& L, int per, int cap, const std::vector<int2>& map,
+                         size_t lds, int wform) {
+  L.per = per;
+  L.cap = cap;
+  L.lds = lds;
+  L.wform = wform;
+  L.n_blocks = (int32_t)map.size();
+  const size_t nb = (size_t)2 * cap * per * sizeof(sd::SliceArgs);
+  hipError_t e = hipMalloc((void**)&L.d_args, nb);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&L.h_args, nb, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&L.d_map, map.size() * sizeof(int2));
+  if (e == hipSuccess)
+    e = hipMemcpy(L.d_map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice);
+  for (int h = 0; h < 2 && e == hipSuccess; ++h) e = hipEventCreateWithFlags(&L.ev[h], hipEventDisableTiming);
+  return e;
+}
+
+void launcher_free(SliceLauncher& L) {
+  for (int h = 0; h < 2; ++h)
+    if (L.ev[h]) (void)hipEventDestroy(L.ev[h]);
+  if (L.d_args) (void)hipFree(L.d_args);
+  if (L.h_args) (void)hipHostFree(L.h_args);
+  if (L.d_map) (void)hipFree(L.d_map);
+  L = SliceLauncher();
+}
+
+// Launch n_slices fused slices whose arguments are list[k * per + i].
+hipError_t launcher_run(SliceLauncher& L, hipStream_t s, const sd::SliceArgs* list,
+                        int64_t n_slices) {
+  for (int64_t k0 = 0; k0 < n_slices; k0 += L.cap) {
+    const int64_t k = std::min<int64_t>(L.cap, n_slices - k0);
+    const int h = L.half;
+    if (L.pend[h]) {
+      hipError_t e = hipEventSynchronize(L.ev[h]);
+      if (e != hipSuccess) return e;
+    }
+    sd::SliceArgs* hs = L.h_args + (size_t)h * L.cap * L.per;
+    sd::SliceArgs* ds = L.d_args + (size_t)h * L.cap * L.per;
+    std::memcpy(hs, list + k0 * L.per, (size_t)k * L.per * sizeof(sd::SliceArgs));
+    hipError_t e = hipMemcpyAsync(ds, hs, (size_t)k * L.per * sizeof(sd::SliceArgs),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(L.ev[h], s);
+    if (e != hipSuccess) return e;
+    L.pend[h] = true;
+    for (int64_t i = 0; i < k; ++i) {
+      e = sd::launch_slice(s, ds + i * L.per, L.d_map, L.n_blocks, L.lds, L.wform);
+      if (e != hipSuccess) return e;
+    }
+    L.half ^= 1;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
 struct sd_ctx {
   sd_config cfg;
   sd_sizes sz;
@@ -178,6 +267,16 @@ struct sd_ctx {
   int32_t count_mode = 0;
   int64_t slices = 0;
   int64_t rec_read = 0;     // raster entries already drained
+  SliceLauncher lau;        // this network alone
+};
+
+// Independent networks advanced together: every slice of all members is
+// one fused launch over the union of their target blocks.
+struct sd_batch {
+  std::vector<sd_ctx*> nets;
+  hipStream_t stream = nullptr;
+  std::string err;
+  SliceLauncher lau;
 };
 
 namespace {
@@ -332,7 +431,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
 }
 
 sd_status launch_slice_checked(sd_ctx* c, const SliceArgs& a) {
-  HIP_TRY(c, launch_slice(c->stream, a, c->cfg.wform));
+  HIP_TRY(c, launcher_run(c->lau, c->stream, &a, 1));
   return SD_OK;
 }
 
@@ -597,10 +696,13 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max) + 64;
-  if ((size_t)lds_max < lds)
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max);
+  if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
+  std::vector<int2> blocks((size_t)c->NB);
+  for (int32_t b = 0; b < c->NB; ++b) blocks[(size_t)b] = make_int2(0, b);
+  HIP_TRY(c, launcher_init(c->lau, 1, 256, xcd_map(blocks), lds, g.wform));
   return SD_OK;
 }
 
@@ -611,6 +713,7 @@ void sd_destroy(sd_ctx* c) {
   if (c->in_list) (void)hipFree(c->in_list);
   if (c->in_off) (void)hipFree(c->in_off);
   if (c->in_cnt) (void)hipFree(c->in_cnt);
+  launcher_free(c->lau);
   delete c;
 }
 
@@ -813,52 +916,81 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
 }
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+// Arguments of the next fused launch from an aligned t_now: deliver the
+// pending slice (if any), update m <= d_min steps, and start a new list;
+// advances the host state as if the launch had run.
+sd_status next_fused_slice(sd_ctx* c, int32_t m, SliceArgs* out) {
+  const sd_config& g = c->cfg;
+  const int32_t Dmin = g.d_min;
+  SliceArgs a = base_args(c);
+  const bool deliver = c->pend_open;
+  if (deliver) {
+    sd_status s = set_pending_input(c, a);
+    if (s != SD_OK) return s;
+    a.do_deliver = 1;
+    a.w_lo = c->pend_t0 + Dmin;  // == t_now
+  }
+  a.rb_hi = c->rb_hi;
+  a.n_upd = m;
+  a.t_upd = c->t_now;
+  a.t_slice0 = c->t_now;
+  const int nxt = c->cur ^ 1;
+  const int cn = (c->ci + 1) % 3;
+  a.out_list = c->list[nxt];
+  a.out_cnt = c->cnt3 + cn;
+  a.zero_cnt = c->cnt3 + (cn + 1) % 3;
+  if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
+  c->cur = nxt;
+  c->ci = cn;
+  c->pend_open = true;
+  c->pend_t0 = c->t_now;
+  c->t_now += m;
+  c->slices += 1;
+  *out = a;
+  return SD_OK;
+}
+}  // namespace
+
+extern "C" {
+
 sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
   if (!c || n_steps < 0) return fail(c, SD_EINVAL, "bad step count");
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
-  const sd_config& g = c->cfg;
-  const int32_t Dmin = g.d_min;
+  const int32_t Dmin = c->cfg.d_min;
+  std::vector<SliceArgs> queue;  // fused launches not yet issued
+  auto flush = [&]() -> sd_status {
+    if (!queue.empty()) {
+      HIP_TRY(c, launcher_run(c->lau, c->stream, queue.data(), (int64_t)queue.size()));
+      queue.clear();
+    }
+    return SD_OK;
+  };
   int64_t left = n_steps;
   while (left > 0) {
     const int64_t in_slice = c->t_now % Dmin;
     if (in_slice != 0) {
       // finish the open slice without delivering (its spikes are not due)
       const int32_t m = (int32_t)std::min<int64_t>(left, Dmin - in_slice);
-      sd_status s = sd_update_neurons(c, m);
+      sd_status s = flush();
+      if (s == SD_OK) s = sd_update_neurons(c, m);
       if (s != SD_OK) return s;
       left -= m;
       continue;
     }
     const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);
-    SliceArgs a = base_args(c);
-    const bool deliver = c->pend_open;
-    if (deliver) {
-      sd_status s = set_pending_input(c, a);
-      if (s != SD_OK) return s;
-      a.do_deliver = 1;
-      a.w_lo = c->pend_t0 + Dmin;  // == t_now
+    SliceArgs a;
+    sd_status s = next_fused_slice(c, m, &a);
+    if (s != SD_OK) {
+      flush();
+      return s;
     }
-    a.rb_hi = c->rb_hi;
-    a.n_upd = m;
-    a.t_upd = c->t_now;
-    a.t_slice0 = c->t_now;
-    const int nxt = c->cur ^ 1;
-    const int cn = (c->ci + 1) % 3;
-    a.out_list = c->list[nxt];
-    a.out_cnt = c->cnt3 + cn;
-    a.zero_cnt = c->cnt3 + (cn + 1) % 3;
-    sd_status s = launch_slice_checked(c, a);
-    if (s != SD_OK) return s;
-    if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
-    c->cur = nxt;
-    c->ci = cn;
-    c->pend_open = true;
-    c->pend_t0 = c->t_now;
-    c->t_now += m;
-    c->slices += 1;
+    queue.push_back(a);
     left -= m;
   }
-  return SD_OK;
+  return flush();
 }
 
 sd_status sd_simulate(sd_ctx* c, double t_ms) {
@@ -1146,6 +1278,131 @@ sd_status sd_get_tables(sd_ctx* c, float* h_we, float* h_wi, uint32_t* h_thr, in
   if (h_prop) HIP_TRY(c, hipMemcpy(h_prop, c->prop64, 7 * 8, hipMemcpyDeviceToHost));
   if (h_prop32) HIP_TRY(c, hipMemcpy(h_prop32, c->prop32, 8 * 4, hipMemcpyDeviceToHost));
   return SD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched networks
+// ---------------------------------------------------------------------------
+namespace {
+sd_status bfail(sd_batch* bt, sd_status st, const std::string& msg) {
+  if (bt) bt->err = msg;
+  return st;
+}
+}  // namespace
+
+sd_status sd_batch_create(const sd_config* cfgs, int32_t n, void* hip_stream, sd_batch** out) {
+  if (!out) return SD_EINVAL;
+  *out = nullptr;
+  auto* bt = new sd_batch;
+  *out = bt;
+  bt->stream = (hipStream_t)hip_stream;
+  if (!cfgs || n < 1) return bfail(bt, SD_EINVAL, "empty batch");
+  const sd_config& c0 = cfgs[0];
+  for (int32_t i = 0; i < n; ++i) {
+    const sd_config& ci = cfgs[i];
+    if (ci.model != c0.model || ci.wform != c0.wform || ci.h != c0.h || ci.d_min != c0.d_min)
+      return bfail(bt, SD_EINVAL,
+                   "member " + std::to_string(i) + ": model, weight form, h and d_min must match");
+    if (open_loop(ci))
+      return bfail(bt, SD_EUNSUPPORTED, "member " + std::to_string(i) + ": open loop");
+  }
+  std::vector<int2> blocks;
+  size_t lds = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    sd_ctx* c = nullptr;
+    const sd_status st = sd_create(&cfgs[i], hip_stream, nullptr, 0, &c);
+    if (st != SD_OK) {
+      const std::string m = "member " + std::to_string(i) + ": " + sd_last_error(c);
+      sd_destroy(c);
+      return bfail(bt, st, m);
+    }
+    bt->nets.push_back(c);
+    for (int32_t b = 0; b < c->NB; ++b) blocks.push_back(make_int2(i, b));
+    lds = std::max(lds, slice_lds_bytes(c->B, cfgs[i].d_min, cfgs[i].d_max));
+  }
+  const hipError_t e = launcher_init(bt->lau, n, 256, xcd_map(blocks), lds, c0.wform);
+  if (e != hipSuccess)
+    return bfail(bt, SD_EHIP, std::string("launcher set-up failed: ") + hipGetErrorString(e));
+  return SD_OK;
+}
+
+void sd_batch_destroy(sd_batch* bt) {
+  if (!bt) return;
+  if (bt->stream || !bt->nets.empty()) (void)hipStreamSynchronize(bt->stream);
+  for (sd_ctx* c : bt->nets) sd_destroy(c);
+  launcher_free(bt->lau);
+  delete bt;
+}
+
+const char* sd_batch_last_error(const sd_batch* bt) { return bt ? bt->err.c_str() : "null batch"; }
+
+int32_t sd_batch_size(const sd_batch* bt) { return bt ? (int32_t)bt->nets.size() : 0; }
+
+sd_ctx* sd_batch_member(sd_batch* bt, int32_t i) {
+  if (!bt || i < 0 || i >= (int32_t)bt->nets.size()) return nullptr;
+  return bt->nets[(size_t)i];
+}
+
+sd_status sd_batch_build(sd_batch* bt) {
+  if (!bt) return SD_EINVAL;
+  for (size_t i = 0; i < bt->nets.size(); ++i) {
+    const sd_status st = sd_build_connections(bt->nets[i]);
+    if (st != SD_OK)
+      return bfail(bt, st, "member " + std::to_string(i) + ": " + sd_last_error(bt->nets[i]));
+  }
+  return SD_OK;
+}
+
+sd_status sd_batch_simulate_steps(sd_batch* bt, int64_t n_steps) {
+  if (!bt || n_steps < 0) return SD_EINVAL;
+  const size_t n = bt->nets.size();
+  if (n == 0) return SD_OK;
+  const int64_t t0 = bt->nets[0]->t_now;
+  for (size_t i = 0; i < n; ++i) {
+    if (!bt->nets[i]->built) return bfail(bt, SD_ESTATE, "build the batch first");
+    if (bt->nets[i]->t_now != t0)
+      return bfail(bt, SD_ESTATE, "members were advanced separately (t_now differs)");
+  }
+  const int32_t Dmin = bt->nets[0]->cfg.d_min;
+  std::vector<SliceArgs> queue;  // n argument structs per fused launch
+  auto flush = [&]() -> sd_status {
+    if (!queue.empty()) {
+      const hipError_t e =
+          launcher_run(bt->lau, bt->stream, queue.data(), (int64_t)(queue.size() / n));
+      if (e != hipSuccess) return bfail(bt, SD_EHIP, hipGetErrorString(e));
+      queue.clear();
+    }
+    return SD_OK;
+  };
+  int64_t left = n_steps;
+  while (left > 0) {
+    const int64_t in_slice = bt->nets[0]->t_now % Dmin;
+    if (in_slice != 0) {
+      const int32_t m = (int32_t)std::min<int64_t>(left, Dmin - in_slice);
+      sd_status st = flush();
+      for (size_t i = 0; i < n && st == SD_OK; ++i) {
+        st = sd_update_neurons(bt->nets[i], m);
+        if (st != SD_OK) bfail(bt, st, sd_last_error(bt->nets[i]));
+      }
+      if (st != SD_OK) return st;
+      left -= m;
+      continue;
+    }
+    const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);
+    for (size_t i = 0; i < n; ++i) {
+      SliceArgs a;
+      const sd_status st = next_fused_slice(bt->nets[i], m, &a);
+      if (st != SD_OK) return bfail(bt, st, sd_last_error(bt->nets[i]));
+      queue.push_back(a);
+    }
+    left -= m;
+  }
+  return flush();
+}
+
+sd_status sd_batch_simulate(sd_batch* bt, double t_ms) {
+  if (!bt || bt->nets.empty() || !(t_ms >= 0.0)) return SD_EINVAL;
+  return sd_batch_simulate_steps(bt, (int64_t)std::llround(t_ms / bt->nets[0]->cfg.h));
 }
 
 }  // extern "C"

@@ -114,7 +114,9 @@ hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_
                        int64_t n_tiles_cap);
 hipError_t launch_fill(hipStream_t s, const BuildArgs& a);
 hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a);
-hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform);
+// one fused slice: workgroup gx serves block map[gx].y of network map[gx].x
+hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_map,
+                        int32_t n_blocks, size_t lds, int wform);
 size_t slice_lds_bytes(int B, int Dmin, int Dmax);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);

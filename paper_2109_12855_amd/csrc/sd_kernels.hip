@@ -409,14 +409,10 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax) 
 
 size_t slice_lds_bytes(int B, int Dmin, int Dmax) { return slice_lds_layout(B, Dmin, Dmax).total; }
 
+// One workgroup's slice for target block b of the network described by a.
 template <int WF>
-__global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
+__device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int gx = blockIdx.x;
-  // XCD-aware mapping: consecutive blocks run on the same XCD so they share
-  // segment-pointer lines and segment boundaries in that XCD's L2.
-  const int b = (gx & 7) * a.grid_per_xcd + (gx >> 3);
-  if (b >= a.NB) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -822,6 +818,22 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice(SliceArgs a) {
   }
 }
 
+// Workgroup gx serves target block map[gx].y of network map[gx].x (one
+// network, or the members of a batch), whose arguments for this slice are
+// args[map[gx].x]; map[gx].x < 0 marks a padding workgroup.  The map is
+// XCD-aware: workgroups gx and gx + 8 run on the same XCD, and consecutive
+// blocks of a network are placed on one XCD so they share segment-pointer
+// lines in its L2.  Arguments live in device memory, so the compiler loads
+// fields where they are used instead of holding the whole struct in
+// scalar registers.
+template <int WF>
+__global__ void __launch_bounds__(kSliceThreads)
+    k_slice(const SliceArgs* __restrict__ args, const int2* __restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  if (m.x < 0) return;
+  slice_block<WF>(args[m.x], m.y);
+}
+
 // ---------------------------------------------------------------------------
 // helpers: ring gap zeroing, open-loop input schedule, decoded export
 // ---------------------------------------------------------------------------
@@ -925,21 +937,22 @@ hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_slice(hipStream_t s, const SliceArgs& a, int wform) {
-  const size_t lds = slice_lds_bytes(a.B, a.Dmin, a.Dmax);
-  const dim3 grid((unsigned)(8 * a.grid_per_xcd)), block(kSliceThreads);
+hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_map,
+                        int32_t n_blocks, size_t lds, int wform) {
+  if (n_blocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n_blocks), block(kSliceThreads);
   switch (wform) {
     case WF_FP32:
-      hipLaunchKernelGGL(k_slice<WF_FP32>, grid, block, lds, s, a);
+      hipLaunchKernelGGL(k_slice<WF_FP32>, grid, block, lds, s, d_args, d_map);
       break;
     case WF_BF16:
-      hipLaunchKernelGGL(k_slice<WF_BF16>, grid, block, lds, s, a);
+      hipLaunchKernelGGL(k_slice<WF_BF16>, grid, block, lds, s, d_args, d_map);
       break;
     case WF_PACKED:
-      hipLaunchKernelGGL(k_slice<WF_PACKED>, grid, block, lds, s, a);
+      hipLaunchKernelGGL(k_slice<WF_PACKED>, grid, block, lds, s, d_args, d_map);
       break;
     default:
-      hipLaunchKernelGGL(k_slice<WF_BF16_RESID>, grid, block, lds, s, a);
+      hipLaunchKernelGGL(k_slice<WF_BF16_RESID>, grid, block, lds, s, d_args, d_map);
       break;
   }
   return hipGetLastError();

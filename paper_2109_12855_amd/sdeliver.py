@@ -76,7 +76,9 @@ EXPORTS = (
     "sd_set_count_mode", "sd_prepare_input", "sd_t_now", "sd_get_sizes", "sd_get_stats",
     "sd_read_ring", "sd_read_state", "sd_write_state", "sd_get_spikes", "sd_get_pending",
     "sd_export_connections", "sd_export_segments", "sd_export_block", "sd_get_tables",
-    "sd_host_tables",
+    "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
+    "sd_batch_size", "sd_batch_member", "sd_batch_build", "sd_batch_simulate_steps",
+    "sd_batch_simulate",
 )
 
 _lib = None
@@ -117,6 +119,14 @@ def lib():
         "sd_get_tables": ([vp, vp, vp, vp, P(i32), vp, vp], i32),
         "sd_export_block": ([vp, i32, vp, vp, vp, vp, P(i64)], i32),
         "sd_host_tables": ([P(sd_config), vp, vp, vp, P(i32)], i32),
+        "sd_batch_create": ([P(sd_config), i32, vp, P(vp)], i32),
+        "sd_batch_destroy": ([vp], None),
+        "sd_batch_last_error": ([vp], C.c_char_p),
+        "sd_batch_size": ([vp], i32),
+        "sd_batch_member": ([vp, i32], vp),
+        "sd_batch_build": ([vp], i32),
+        "sd_batch_simulate_steps": ([vp, i64], i32),
+        "sd_batch_simulate": ([vp, dbl], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -212,7 +222,26 @@ class Net:
         if rc != SD_OK:
             raise SdError(rc, f"{what}: {lib().sd_last_error(self._h).decode()}")
 
+    @classmethod
+    def _member(cls, cfg: dict, handle, owner):
+        """A batch member: a borrowed context (the batch owns and frees it)."""
+        self = cls.__new__(cls)
+        self.cfg = dict(cfg)
+        self._c = make_config(self.cfg)
+        self.sizes = query_sizes(self.cfg)
+        self.arena = None
+        self._h = C.c_void_p(handle)
+        self._owner = owner
+        self.n_local = int(self.sizes["n_local"])
+        self.n_src = int(self.sizes["n_src"])
+        self.n_syn = int(self.sizes["n_syn"])
+        self.ring_len = int(self.cfg["ring_len"])
+        return self
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = None  # borrowed from a batch
+            return
         if getattr(self, "_h", None):
             lib().sd_destroy(self._h)
             self._h = None
@@ -348,3 +377,58 @@ class Net:
         self._check(lib().sd_get_tables(self._h, _ptr(we), _ptr(wi), _ptr(thr), C.byref(n),
                                         _ptr(p64), _ptr(p32)), "sd_get_tables")
         return {"w_e": we, "w_i": wi, "thr": thr[: n.value].copy(), "prop": p64, "prop32": p32}
+
+
+class Batch:
+    """Independent networks advanced together, one fused launch per slice.
+
+    ``Batch(cfgs)`` creates one context per config (library-allocated
+    device memory, torch's current stream), ``build()`` lays out every
+    member, ``simulate_steps(n)`` advances all members; ``members[i]`` is a
+    borrowed ``Net`` for read-back (spikes, state, ring, stats).
+    """
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+
+        self.cfgs = [dict(c) for c in cfgs]
+        arr = (sd_config * len(self.cfgs))(*[make_config(c) for c in self.cfgs])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = lib().sd_batch_create(arr, len(self.cfgs), C.c_void_p(self.stream.cuda_stream),
+                                   C.byref(h))
+        self._h = h
+        if rc != SD_OK:
+            msg = lib().sd_batch_last_error(h).decode() if h else ""
+            lib().sd_batch_destroy(h)
+            self._h = None
+            raise SdError(rc, msg)
+        self.members = [Net._member(c, lib().sd_batch_member(self._h, i), self)
+                        for i, c in enumerate(self.cfgs)]
+
+    def _check(self, rc: int, what: str):
+        if rc != SD_OK:
+            raise SdError(rc, f"{what}: {lib().sd_batch_last_error(self._h).decode()}")
+
+    def build(self):
+        self._check(lib().sd_batch_build(self._h), "sd_batch_build")
+        return self
+
+    def simulate_steps(self, n: int):
+        self._check(lib().sd_batch_simulate_steps(self._h, int(n)), "sd_batch_simulate_steps")
+
+    def simulate(self, t_ms: float):
+        self._check(lib().sd_batch_simulate(self._h, float(t_ms)), "sd_batch_simulate")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m._h = None
+            lib().sd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
