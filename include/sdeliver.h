@@ -178,6 +178,18 @@ sd_status sd_read_ring(sd_ctx* ctx, float* h_out, int32_t n_slots);
 sd_status sd_read_state(sd_ctx* ctx, float* h_v, float* h_y1, float* h_y2, int32_t* h_r);
 sd_status sd_write_state(sd_ctx* ctx, const float* h_v, const float* h_y1, const float* h_y2,
                          const int32_t* h_r);
+/* Checkpoint / resume.  sd_save_state writes the dynamic state (neuron
+ * state, ring buffers, the open slice's spikes, step counters and event
+ * statistics) into h_buf (cap bytes; h_buf NULL: only *used is set to the
+ * size needed).  sd_load_state restores it into a built context of the same
+ * configuration (SD_EINVAL otherwise): the connection table is not saved,
+ * it is redrawn deterministically by sd_build_connections.  Not saved: the
+ * spike raster and an open-loop input schedule (call sd_prepare_input
+ * again after loading).  A resumed run gives the same results as an
+ * uninterrupted one.  (A service for long runs, not an operation of the
+ * method itself.) */
+sd_status sd_save_state(sd_ctx* ctx, void* h_buf, size_t cap, size_t* used);
+sd_status sd_load_state(sd_ctx* ctx, const void* h_buf, size_t n);
 /* drain the raster: (step, neuron) pairs in emission-slice order */
 sd_status sd_get_spikes(sd_ctx* ctx, int64_t* h_step, uint32_t* h_id, int64_t cap, int64_t* n);
 /* spikes of the open (not yet delivered) slice */

@@ -1099,6 +1099,132 @@ sd_status sd_write_state(sd_ctx* c, const float* h_v, const float* h_y1, const f
   return SD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Checkpoint layout (host byte buffer): StateHeader, then V, y1, y2, r
+// (N x 4 B each), the ring rows [L][N] (FP32), and the open slice's spike
+// entries (n_pending x 4 B).  The connection table is not part of it: it is
+// redrawn from the configuration by sd_build_connections.
+struct StateHeader {
+  char magic[8];
+  uint64_t cfg_hash;
+  int64_t N, t_now, rb_hi, pend_t0, slices, n_pending, rec_read;
+  int32_t L, pend_open, count_mode, overflow;
+  uint64_t counters[4];
+};
+constexpr char kStateMagic[8] = {'S', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
+
+uint64_t config_hash(const sd_config& g) {
+  uint64_t h = 1469598103934665603ULL;  // FNV-1a over the fields, one by one
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ULL;
+  };
+#define SD_MIX(f) mix(&g.f, sizeof g.f)
+  SD_MIX(model); SD_MIX(wform); SD_MIX(n_exc); SD_MIX(n_inh); SD_MIX(n_src_exc);
+  SD_MIX(n_src_inh); SD_MIX(k_exc); SD_MIX(k_inh); SD_MIX(d_lo); SD_MIX(d_hi); SD_MIX(d_min);
+  SD_MIX(d_max); SD_MIX(ring_len); SD_MIX(h); SD_MIX(w_exc); SD_MIX(w_cv); SD_MIX(g);
+  SD_MIX(tau_m); SD_MIX(c_m); SD_MIX(tau_syn); SD_MIX(e_l); SD_MIX(v_th); SD_MIX(v_reset);
+  SD_MIX(t_ref); SD_MIX(i_e); SD_MIX(v0_lo); SD_MIX(v0_hi); SD_MIX(drive_rate_hz);
+  SD_MIX(drive_w); SD_MIX(src_rate_hz); SD_MIX(seed); SD_MIX(block_neurons);
+#undef SD_MIX
+  return h;
+}
+}  // namespace
+
+extern "C" {
+
+sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
+  if (!c || !used) return SD_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int32_t L = c->cfg.ring_len;
+  int64_t n_pend = 0;
+  if (c->pend_open && !open_loop(c->cfg)) {
+    int32_t cnt = 0;
+    HIP_TRY(c, hipMemcpy(&cnt, c->cnt3 + c->ci, 4, hipMemcpyDeviceToHost));
+    n_pend = std::min<int64_t>(cnt, c->list_cap);
+  }
+  const size_t need = sizeof(StateHeader) + (size_t)c->N * 16 + (size_t)L * c->N * 4 +
+                      (size_t)n_pend * 4;
+  *used = need;
+  if (!h_buf) return SD_OK;
+  if (cap < need) return fail(c, SD_EINVAL, "buffer of %zu B < %zu needed", cap, need);
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, kStateMagic, 8);
+  hd.cfg_hash = config_hash(c->cfg);
+  hd.N = c->N;
+  hd.t_now = c->t_now;
+  hd.rb_hi = c->rb_hi;
+  hd.pend_t0 = c->pend_t0;
+  hd.slices = c->slices;
+  hd.n_pending = n_pend;
+  hd.rec_read = c->rec_read;
+  hd.L = L;
+  hd.pend_open = c->pend_open ? 1 : 0;
+  hd.count_mode = c->count_mode;
+  HIP_TRY(c, hipMemcpy(hd.counters, c->counters, 32, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&hd.overflow, c->overflow, 4, hipMemcpyDeviceToHost));
+  char* p = (char*)h_buf;
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  const size_t n4 = (size_t)c->N * 4;
+  HIP_TRY(c, hipMemcpy(p, c->V, n4, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(p + n4, c->y1, n4, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(p + 2 * n4, c->y2, n4, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(p + 3 * n4, c->r, n4, hipMemcpyDeviceToHost));
+  p += 4 * n4;
+  HIP_TRY(c, hipMemcpy(p, c->rb, (size_t)L * n4, hipMemcpyDeviceToHost));
+  p += (size_t)L * n4;
+  if (n_pend > 0) HIP_TRY(c, hipMemcpy(p, c->list[c->cur], (size_t)n_pend * 4, hipMemcpyDeviceToHost));
+  return SD_OK;
+}
+
+sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
+  if (!c || !h_buf) return SD_EINVAL;
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  if (n < sizeof(StateHeader)) return fail(c, SD_EINVAL, "state buffer too short");
+  StateHeader hd;
+  std::memcpy(&hd, h_buf, sizeof hd);
+  if (std::memcmp(hd.magic, kStateMagic, 8) != 0) return fail(c, SD_EINVAL, "not a state buffer");
+  if (hd.cfg_hash != config_hash(c->cfg) || hd.N != c->N || hd.L != c->cfg.ring_len)
+    return fail(c, SD_EINVAL, "state was saved from a different configuration");
+  const size_t n4 = (size_t)c->N * 4;
+  const size_t need = sizeof hd + 4 * n4 + (size_t)hd.L * n4 + (size_t)hd.n_pending * 4;
+  if (n < need || hd.n_pending < 0 || hd.n_pending > c->list_cap)
+    return fail(c, SD_EINVAL, "state buffer holds %zu B, %zu needed", n, need);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const char* p = (const char*)h_buf + sizeof hd;
+  HIP_TRY(c, hipMemcpy(c->V, p, n4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->y1, p + n4, n4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->y2, p + 2 * n4, n4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->r, p + 3 * n4, n4, hipMemcpyHostToDevice));
+  p += 4 * n4;
+  HIP_TRY(c, hipMemcpy(c->rb, p, (size_t)hd.L * n4, hipMemcpyHostToDevice));
+  p += (size_t)hd.L * n4;
+  // the open slice's list goes to list 0 with counter 0; counter 1 (the
+  // next list's) must be zero
+  c->cur = 0;
+  c->ci = 0;
+  const int32_t cnt[3] = {(int32_t)hd.n_pending, 0, 0};
+  HIP_TRY(c, hipMemcpy(c->cnt3, cnt, 12, hipMemcpyHostToDevice));
+  if (hd.n_pending > 0)
+    HIP_TRY(c, hipMemcpy(c->list[0], p, (size_t)hd.n_pending * 4, hipMemcpyHostToDevice));
+  // the raster is not saved: it restarts empty
+  hd.counters[3] = 0;
+  HIP_TRY(c, hipMemcpy(c->counters, hd.counters, 32, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->overflow, &hd.overflow, 4, hipMemcpyHostToDevice));
+  c->t_now = hd.t_now;
+  c->rb_hi = hd.rb_hi;
+  c->pend_t0 = hd.pend_t0;
+  c->pend_open = hd.pend_open != 0;
+  c->slices = hd.slices;
+  c->count_mode = hd.count_mode;
+  c->rec_read = 0;
+  return SD_OK;
+}
+
 sd_status sd_get_spikes(sd_ctx* c, int64_t* h_step, uint32_t* h_id, int64_t cap, int64_t* n) {
   if (!c || !n) return SD_EINVAL;
   *n = 0;

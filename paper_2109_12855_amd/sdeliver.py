@@ -78,7 +78,7 @@ EXPORTS = (
     "sd_export_connections", "sd_export_segments", "sd_export_block", "sd_get_tables",
     "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
     "sd_batch_size", "sd_batch_member", "sd_batch_build", "sd_batch_simulate_steps",
-    "sd_batch_simulate",
+    "sd_batch_simulate", "sd_save_state", "sd_load_state",
 )
 
 _lib = None
@@ -119,6 +119,8 @@ def lib():
         "sd_get_tables": ([vp, vp, vp, vp, P(i32), vp, vp], i32),
         "sd_export_block": ([vp, i32, vp, vp, vp, vp, P(i64)], i32),
         "sd_host_tables": ([P(sd_config), vp, vp, vp, P(i32)], i32),
+        "sd_save_state": ([vp, vp, C.c_size_t, P(C.c_size_t)], i32),
+        "sd_load_state": ([vp, vp, C.c_size_t], i32),
         "sd_batch_create": ([P(sd_config), i32, vp, P(vp)], i32),
         "sd_batch_destroy": ([vp], None),
         "sd_batch_last_error": ([vp], C.c_char_p),
@@ -325,6 +327,18 @@ class Net:
         st, idx = st[: n.value], idx[: n.value]
         order = np.lexsort((idx, st))
         return st[order], idx[order]
+
+    def save_state(self) -> bytes:
+        """Checkpoint of the dynamic state (see sd_save_state)."""
+        n = C.c_size_t()
+        self._check(lib().sd_save_state(self._h, None, 0, C.byref(n)), "sd_save_state")
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().sd_save_state(self._h, buf, n.value, C.byref(n)), "sd_save_state")
+        return buf.raw[: n.value]
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(lib().sd_load_state(self._h, buf, len(data)), "sd_load_state")
 
     def pending(self):
         cap = self.n_local * int(self.cfg["d_min"])
