@@ -60,7 +60,26 @@ typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
  *   SD_W_BF16_PACKED the residual weight (low half) and the ring-window slot
  *                    (delay - d_min) * block_neurons + offset in block
  *                    (high half) in one 32-bit word             (4 B);
- *                    needs (d_max - d_min + 1) * block_neurons <= 65536   */
+ *                    needs (d_max - d_min + 1) * block_neurons <= 65536
+ * In the source-major layout a record is a u32 {target (26 bits), delay -
+ * d_min (6 bits)} plus the weight: f32 (FP32 form, 8 B) or the u16 BF16 /
+ * residual bits (the BF16 forms; packed = residual there, 6 B). */
+/* Connection-table layout:
+ *   SD_LAYOUT_BLOCK   block-major: the synapses into each target block of B
+ *                     neurons, grouped by source; a workgroup delivers into
+ *                     its block's ring window held in LDS.  For networks
+ *                     whose sources each reach many targets per block.
+ *   SD_LAYOUT_SOURCE  source-major: each source's synapses to all local
+ *                     targets form one contiguous segment (as in the
+ *                     paper's per-process table, Sec. 3.1); deliveries go
+ *                     into a 64-bit fixed-point ring in device memory by
+ *                     global integer atomics.  For tables beyond 2^32
+ *                     synapses and sources whose segments are sparse across
+ *                     blocks (the one-GPU share of a brain-scale network).
+ *   SD_LAYOUT_AUTO    block-major when it fits, else source-major.
+ * Both give the same sums (exact integers in the fixed-point window). */
+typedef enum { SD_LAYOUT_AUTO = 0, SD_LAYOUT_BLOCK = 1, SD_LAYOUT_SOURCE = 2 } sd_layout;
+
 typedef enum {
   SD_W_FP32 = 0,
   SD_W_BF16 = 1,
@@ -89,6 +108,7 @@ typedef struct {
   int32_t block_neurons;     /* target block size (0 = automatic)               */
   int32_t record_spikes;     /* keep a device raster of emitted spikes (0/1)    */
   int64_t record_cap;        /* raster capacity in spikes (0 = automatic)       */
+  int32_t layout;            /* sd_layout                                       */
 } sd_config;
 
 typedef struct {
@@ -99,7 +119,9 @@ typedef struct {
   int32_t n_blocks;          /* number of target blocks                         */
   int64_t table_bytes;       /* synapse arrays + segment pointers               */
   int64_t arena_bytes;       /* total device memory of a context                */
-  int32_t bytes_per_synapse; /* 9 (FP32), 5 (BF16, BF16 residual), 4 (packed)   */
+  int32_t bytes_per_synapse; /* block-major: 9 (FP32), 5 (BF16, residual), 4
+                                (packed); source-major: 8 (FP32), 6 (BF16s)   */
+  int32_t layout;            /* the layout in use (SD_LAYOUT_BLOCK / _SOURCE)   */
 } sd_sizes;
 
 typedef struct {
@@ -195,12 +217,16 @@ sd_status sd_get_spikes(sd_ctx* ctx, int64_t* h_step, uint32_t* h_id, int64_t ca
 /* spikes of the open (not yet delivered) slice */
 sd_status sd_get_pending(sd_ctx* ctx, uint32_t* h_src, uint8_t* h_lag, int64_t cap, int64_t* n,
                          int64_t* slice_t0);
-/* connection table in canonical (source, target, draw) order, decoded:
- * h_row[n_src+1] (int64), h_tgt[n_syn], h_dly[n_syn], h_w[n_syn] */
+/* connection table, decoded: h_row[n_src+1] (int64), h_tgt[n_syn],
+ * h_dly[n_syn], h_w[n_syn]; each source's synapses in (target, draw)
+ * order (block-major layout) or (target, delay, weight) order
+ * (source-major layout, which does not keep draw indices) */
 sd_status sd_export_connections(sd_ctx* ctx, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
                                 float* h_w);
 /* where one source's segments sit: for every block b, the index of its first
- * synapse into b and their count (h_start[n_blocks], h_len[n_blocks]) */
+ * synapse into b and their count (h_start[n_blocks], h_len[n_blocks]);
+ * block-major layout only (SD_EUNSUPPORTED otherwise), as is
+ * sd_export_block */
 sd_status sd_export_segments(sd_ctx* ctx, int64_t src, int64_t* h_start, int64_t* h_len);
 /* the synapses into target block b, source-major: h_row[n_src+1] (relative
  * to the block's first synapse), then h_tgt/h_dly/h_w of *n_out synapses

@@ -222,6 +222,14 @@ struct sd_ctx {
   uint32_t* row = nullptr;      // block-major segment starts
   uint32_t* cursor = nullptr;
   uint2* seg = nullptr;         // source-major (start, count) pairs
+  // source-major layout
+  bool sm = false;
+  unsigned long long* row64 = nullptr;   // segment starts per source
+  unsigned long long* cursor64 = nullptr;
+  unsigned long long* tiles64 = nullptr;
+  uint32_t* tgtd = nullptr;              // target | (delay - d_min) << 26
+  void* wbits = nullptr;                 // weights (u16 bits or f32)
+  long long* rbq = nullptr;              // 64-bit fixed-point ring [L][N]
   uint32_t* tile_sums = nullptr;
   int64_t n_tiles = 0;
   void* syn = nullptr;          // synapse records
@@ -333,6 +341,7 @@ sd_status check_config(const sd_config* c, std::string* why) {
   if (c->t_ref < 0.0 || c->drive_rate_hz < 0.0 || c->src_rate_hz < 0.0) return bad("negative rate");
   if (c->block_neurons < 0 || (c->block_neurons % 64) != 0) return bad("block_neurons % 64 != 0");
   if (c->w_cv < 0.0) return bad("negative weight CV");
+  if (c->layout < SD_LAYOUT_AUTO || c->layout > SD_LAYOUT_SOURCE) return bad("unknown layout");
   return SD_OK;
 }
 
@@ -342,18 +351,16 @@ struct Layout {
   int64_t N, n_src, n_syn, M, n_tiles, rec_cap;
   int32_t B, NB, rec_bytes, dly_bytes;
   int64_t list_cap;
+  bool sm = false;  // source-major layout
   size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
       off_counters, off_overflow, total;
 };
 
-sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
-  sd_status s = check_config(c, why);
-  if (s != SD_OK) return s;
-  L->N = c->n_exc + c->n_inh;
-  L->n_src = open_loop(*c) ? c->n_src_exc + c->n_src_inh : L->N;
+// Block-major geometry and its limits (LDS window, u16/packed offsets,
+// buffer-resource range, 32-bit segment pointers).
+sd_status block_major_fits(const sd_config* c, Layout* L, std::string* why) {
   const int64_t K = (int64_t)c->k_exc + c->k_inh;
-  L->n_syn = L->N * K;
   L->B = auto_block(*c, L->N);
   L->NB = (int32_t)((L->N + L->B - 1) / L->B);
   if (L->B > 65536 && c->wform != SD_W_FP32) {
@@ -372,40 +379,81 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     *why = "a target block holds more than 2^28 synapses or 1 GiB; lower block_neurons";
     return SD_EUNSUPPORTED;
   }
-  const size_t lds = slice_lds_bytes(L->B, c->d_min, c->d_max);
-  if (lds > 160 * 1024) {
+  if (slice_lds_bytes(L->B, c->d_min, c->d_max) > 160 * 1024) {
     *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
     return SD_EUNSUPPORTED;
   }
-  L->M = L->n_src * L->NB + 1;
   if (L->n_syn >= (int64_t)UINT32_MAX || L->N >= (1LL << 27) || L->n_src >= (1LL << 27)) {
-    *why = "more than 2^32 synapses or 2^27 neurons needs the sparse layout";
+    *why = "block-major layout holds at most 2^32 synapses and 2^27 neurons";
     return SD_EUNSUPPORTED;
+  }
+  // (start, count) pairs of every (source, block): keep them below 8 GiB
+  if ((double)L->n_src * L->NB * 8.0 > 8.0 * (1LL << 30)) {
+    *why = "segment-pointer table of the block-major layout exceeds 8 GiB";
+    return SD_EUNSUPPORTED;
+  }
+  return SD_OK;
+}
+
+sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
+  sd_status s = check_config(c, why);
+  if (s != SD_OK) return s;
+  L->N = c->n_exc + c->n_inh;
+  L->n_src = open_loop(*c) ? c->n_src_exc + c->n_src_inh : L->N;
+  L->n_syn = L->N * ((int64_t)c->k_exc + c->k_inh);
+  if (c->layout == SD_LAYOUT_SOURCE) {
+    L->sm = true;
+  } else {
+    s = block_major_fits(c, L, why);
+    if (s != SD_OK && c->layout == SD_LAYOUT_BLOCK) return s;
+    L->sm = s != SD_OK;
+  }
+  if (L->sm) {
+    if (L->N >= (1LL << kTgtBits) || L->n_src >= (1LL << 27) || c->d_max - c->d_min >= 64) {
+      *why = "source-major layout holds at most 2^26 targets, 2^27 sources and "
+             "d_max - d_min < 64";
+      return SD_EUNSUPPORTED;
+    }
+    // blocks only organise the update: one thread per neuron
+    int64_t b = (L->N + 255) / 256;
+    b = std::max<int64_t>(64, std::min<int64_t>(1024, (b + 63) / 64 * 64));
+    L->B = c->block_neurons > 0 ? c->block_neurons : (int32_t)b;
+    L->NB = (int32_t)((L->N + L->B - 1) / L->B);
+    if (L->B > kSliceThreads) {
+      *why = "source-major layout needs block_neurons <= 1024";
+      return SD_EINVAL;
+    }
+    L->M = L->n_src + 1;
+    L->rec_bytes = 4;                                  // target | delay
+    L->dly_bytes = c->wform == SD_W_FP32 ? 4 : 2;      // weight (f32 or u16 bits)
+  } else {
+    L->M = L->n_src * L->NB + 1;
+    L->rec_bytes = c->wform == SD_W_FP32 ? 8 : 4;
+    L->dly_bytes = c->wform == SD_W_BF16_PACKED ? 0 : 1;
   }
   L->n_tiles = (L->M + 4095) / 4096;
   L->list_cap = (int64_t)L->NB * L->B * c->d_min;
   L->rec_cap = c->record_spikes ? (c->record_cap > 0 ? c->record_cap
                                                      : std::max<int64_t>(1 << 20, L->N * 64))
                                 : 0;
-  L->rec_bytes = c->wform == SD_W_FP32 ? 8 : 4;
-  L->dly_bytes = c->wform == SD_W_BF16_PACKED ? 0 : 1;
+  const size_t ptr = L->sm ? 8 : 4;  // segment pointer width
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o = align_up(o + bytes);
     return at;
   };
-  L->off_row = take((size_t)L->M * 4);
-  L->off_cursor = take((size_t)L->M * 4);
-  L->off_seg = take((size_t)L->n_src * L->NB * 8);
-  L->off_tiles = take((size_t)L->n_tiles * 4);
+  L->off_row = take((size_t)L->M * ptr);
+  L->off_cursor = take((size_t)L->M * ptr);
+  L->off_seg = take(L->sm ? 0 : (size_t)L->n_src * L->NB * 8);
+  L->off_tiles = take((size_t)L->n_tiles * ptr);
   L->off_syn = take((size_t)L->n_syn * L->rec_bytes);
   L->off_dly = take((size_t)L->n_syn * L->dly_bytes);
   L->off_V = take((size_t)L->N * 4);
   L->off_y1 = take((size_t)L->N * 4);
   L->off_y2 = take((size_t)L->N * 4);
   L->off_r = take((size_t)L->N * 4);
-  L->off_rb = take((size_t)c->ring_len * L->N * 4);
+  L->off_rb = take((size_t)c->ring_len * L->N * (L->sm ? 8 : 4));
   L->off_list0 = take((size_t)L->list_cap * 4);
   L->off_list1 = take((size_t)L->list_cap * 4);
   L->off_cnt = take(3 * 4);
@@ -425,8 +473,10 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   z.block_neurons = L->B;
   z.n_blocks = L->NB;
   z.bytes_per_synapse = L->rec_bytes + L->dly_bytes;
-  z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * 4 + L->n_src * L->NB * 8;
+  z.table_bytes = (int64_t)L->n_syn * z.bytes_per_synapse + L->M * (int64_t)ptr +
+                  (L->sm ? 0 : L->n_src * L->NB * 8);
   z.arena_bytes = (int64_t)L->total;
+  z.layout = L->sm ? SD_LAYOUT_SOURCE : SD_LAYOUT_BLOCK;
   return SD_OK;
 }
 
@@ -450,6 +500,7 @@ SliceArgs base_args(sd_ctx* c) {
   a.Dmin = g.d_min;
   a.Dmax = g.d_max;
   a.L = g.ring_len;
+  a.win_rows = c->sm ? 0 : g.d_max;
   a.src_e_end = c->src_e_end;
   {
     // fixed-point weight trunc(m1 * x + m0): x is the weight (FP32, BF16) or
@@ -484,6 +535,7 @@ SliceArgs base_args(sd_ctx* c) {
   a.ref_steps = c->ref_steps;
   a.model = g.model;
   a.rb = c->rb;
+  a.rbq = c->rbq;
   a.rb_hi = c->rb_hi;
   a.write_list = open_loop(g) ? 0 : 1;
   a.out_cap = c->list_cap;
@@ -505,6 +557,45 @@ sd_status fill_gap(sd_ctx* c, int64_t w_lo) {
     HIP_TRY(c, launch_zero_rows(c->stream, c->rb, c->N, c->cfg.ring_len, lo, w_lo));
     c->rb_hi = w_lo;
   }
+  return SD_OK;
+}
+
+// Source-major delivery of n entries of in_list (count on the device) whose
+// slice starts at step t0: rows of the window [t0 + d_min, t0 + d_min +
+// d_max) not yet claimed are zeroed, then the atomic delivery kernel adds
+// every synapse of every spike.
+sd_status sm_deliver(sd_ctx* c, const uint32_t* in_list, const int32_t* in_cnt, int64_t in_cap,
+                     int64_t t0) {
+  const sd_config& g = c->cfg;
+  const int64_t w_lo = t0 + g.d_min;
+  const int64_t lo = std::max(c->t_now, c->rb_hi);
+  HIP_TRY(c, launch_zero_rows64(c->stream, c->rbq, c->N, g.ring_len, lo, w_lo + g.d_max));
+  c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
+  const SliceArgs b = base_args(c);
+  SmDeliverArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.row = c->row64;
+  a.tgtd = c->tgtd;
+  a.wbits = c->wbits;
+  a.wform = g.wform;
+  a.in_list = in_list;
+  a.in_cnt = in_cnt;
+  a.in_cap = in_cap;
+  a.n_src = c->n_src;
+  a.ring = c->rbq;
+  a.N = c->N;
+  a.L = g.ring_len;
+  a.Dmin = g.d_min;
+  a.t0 = t0;
+  a.src_e_end = c->src_e_end;
+  a.wm0_e = b.wm0_e;
+  a.wm1_e = b.wm1_e;
+  a.wm0_i = b.wm0_i;
+  a.wm1_i = b.wm1_i;
+  a.ev_count = c->counters + 0;
+  a.spk_in_count = c->counters + 1;
+  a.overflow = c->overflow;
+  HIP_TRY(c, launch_deliver_sm(c->stream, a));
   return SD_OK;
 }
 
@@ -598,6 +689,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->rec_cap = L.rec_cap;
   c->grid_per_xcd = (L.NB + 7) / 8;
   c->src_e_end = open_loop(*cfg) ? cfg->n_src_exc : cfg->n_exc;
+  c->sm = L.sm;
   *out = c;
   if (d_arena) {
     if (arena_bytes < L.total) return fail(c, SD_ENOMEM, "arena of %zu bytes < %zu needed",
@@ -622,7 +714,22 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->y1 = (float*)(A + L.off_y1);
   c->y2 = (float*)(A + L.off_y2);
   c->r = (int32_t*)(A + L.off_r);
-  c->rb = (float*)(A + L.off_rb);
+  if (c->sm) {
+    c->row64 = (unsigned long long*)(A + L.off_row);
+    c->cursor64 = (unsigned long long*)(A + L.off_cursor);
+    c->tiles64 = (unsigned long long*)(A + L.off_tiles);
+    c->tgtd = (uint32_t*)(A + L.off_syn);
+    c->wbits = A + L.off_dly;
+    c->rbq = (long long*)(A + L.off_rb);
+    c->rb = nullptr;
+    c->row = nullptr;
+    c->cursor = nullptr;
+    c->seg = nullptr;
+    c->syn = nullptr;
+    c->syn_dly = nullptr;
+  } else {
+    c->rb = (float*)(A + L.off_rb);
+  }
   c->list[0] = (uint32_t*)(A + L.off_list0);
   c->list[1] = (uint32_t*)(A + L.off_list1);
   c->cnt3 = (int32_t*)(A + L.off_cnt);
@@ -696,7 +803,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max);
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, c->sm ? 0 : g.d_max);
   if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
@@ -761,6 +868,27 @@ sd_status sd_build_connections(sd_ctx* c) {
   } else if (g.wform == SD_W_BF16_RESID || g.wform == SD_W_BF16_PACKED) {
     a.fix_bits_e = resid_bits(fe, c->mu_e);
     a.fix_bits_i = resid_bits(fi, c->mu_i);
+  }
+  if (c->sm) {
+    a.row64 = c->row64;
+    a.cursor64 = c->cursor64;
+    a.tgtd = c->tgtd;
+    a.wbits = c->wbits;
+    HIP_TRY(c, hipMemsetAsync(c->row64, 0, (size_t)c->M * 8, c->stream));
+    if (c->K > 0) HIP_TRY(c, launch_count_sm(c->stream, a));
+    HIP_TRY(c, launch_scan64(c->stream, c->row64, c->M, c->tiles64, c->n_tiles));
+    HIP_TRY(c, hipMemcpyAsync(c->cursor64, c->row64, (size_t)c->M * 8, hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (c->K > 0) HIP_TRY(c, launch_fill_sm(c->stream, a));
+    HIP_TRY(c, hipMemsetAsync(c->rbq, 0, (size_t)c->cfg.ring_len * c->N * 8, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned long long total = 0;
+    HIP_TRY(c, hipMemcpy(&total, c->row64 + c->M - 1, 8, hipMemcpyDeviceToHost));
+    if ((int64_t)total != c->n_syn)
+      return fail(c, SD_EHIP, "segment table holds %llu synapses, expected %lld", total,
+                  (long long)c->n_syn);
+    c->built = true;
+    return SD_OK;
   }
   HIP_TRY(c, hipMemsetAsync(c->row, 0, (size_t)c->M * 4, c->stream));
   if (c->K > 0) HIP_TRY(c, launch_count(c->stream, a));
@@ -894,6 +1022,23 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
     if (n == 0) a.do_deliver = 0;
   }
   const int64_t w_lo = t0 + g.d_min;
+  if (c->sm) {
+    sd_status s = SD_OK;
+    if (a.do_deliver) {
+      s = sm_deliver(c, a.in_list, a.in_cnt, a.in_cap, t0);
+    } else {
+      const int64_t lo = std::max(c->t_now, c->rb_hi);
+      HIP_TRY(c, launch_zero_rows64(c->stream, c->rbq, c->N, g.ring_len, lo, w_lo + g.d_max));
+      c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
+    }
+    if (packed) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(packed));
+    }
+    if (s != SD_OK) return s;
+    if (own) c->pend_open = false;
+    return SD_OK;
+  }
   sd_status s = fill_gap(c, w_lo);
   if (s != SD_OK) return s;
   a.rb_hi = c->rb_hi;
@@ -942,6 +1087,14 @@ sd_status next_fused_slice(sd_ctx* c, int32_t m, SliceArgs* out) {
   a.out_list = c->list[nxt];
   a.out_cnt = c->cnt3 + cn;
   a.zero_cnt = c->cnt3 + (cn + 1) % 3;
+  if (deliver && c->sm) {
+    // source-major: the delivery is its own launch (issued now); the
+    // fused launch then only updates
+    sd_status s = sm_deliver(c, a.in_list, a.in_cnt, a.in_cap, c->pend_t0);
+    if (s != SD_OK) return s;
+    a.do_deliver = 0;
+    a.rb_hi = c->rb_hi;
+  }
   if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
   c->cur = nxt;
   c->ci = cn;
@@ -982,12 +1135,19 @@ sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
     }
     const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);
     SliceArgs a;
-    sd_status s = next_fused_slice(c, m, &a);
+    // source-major: the delivery launch is issued inside next_fused_slice,
+    // so queued updates go first and this update right after it
+    sd_status s = c->sm ? flush() : SD_OK;
+    if (s == SD_OK) s = next_fused_slice(c, m, &a);
     if (s != SD_OK) {
       flush();
       return s;
     }
     queue.push_back(a);
+    if (c->sm) {
+      s = flush();
+      if (s != SD_OK) return s;
+    }
     left -= m;
   }
   return flush();
@@ -1067,7 +1227,14 @@ sd_status sd_read_ring(sd_ctx* c, float* h_out, int32_t n_slots) {
   for (int32_t s = 0; s < n_slots; ++s) {
     const int64_t t = c->t_now + s;
     float* dst = h_out + (size_t)s * c->N;
-    if (t < c->rb_hi) {
+    if (t < c->rb_hi && c->sm) {
+      // 64-bit fixed-point row, read out as the slice kernel does
+      std::vector<long long> q((size_t)c->N);
+      HIP_TRY(c, hipMemcpy(q.data(), c->rbq + (t % L) * c->N, (size_t)c->N * 8,
+                           hipMemcpyDeviceToHost));
+      const double inv = std::ldexp(1.0, -c->fx_shift);
+      for (int64_t n = 0; n < c->N; ++n) dst[n] = (float)((double)q[(size_t)n] * inv);
+    } else if (t < c->rb_hi) {
       HIP_TRY(c, hipMemcpy(dst, c->rb + (t % L) * c->N, (size_t)c->N * 4, hipMemcpyDeviceToHost));
     } else {
       std::memset(dst, 0, (size_t)c->N * 4);
@@ -1145,7 +1312,8 @@ sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
     HIP_TRY(c, hipMemcpy(&cnt, c->cnt3 + c->ci, 4, hipMemcpyDeviceToHost));
     n_pend = std::min<int64_t>(cnt, c->list_cap);
   }
-  const size_t need = sizeof(StateHeader) + (size_t)c->N * 16 + (size_t)L * c->N * 4 +
+  const size_t cell = c->sm ? 8 : 4;  // fixed-point or FP32 ring cells
+  const size_t need = sizeof(StateHeader) + (size_t)c->N * 16 + (size_t)L * c->N * cell +
                       (size_t)n_pend * 4;
   *used = need;
   if (!h_buf) return SD_OK;
@@ -1175,8 +1343,9 @@ sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
   HIP_TRY(c, hipMemcpy(p + 2 * n4, c->y2, n4, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(p + 3 * n4, c->r, n4, hipMemcpyDeviceToHost));
   p += 4 * n4;
-  HIP_TRY(c, hipMemcpy(p, c->rb, (size_t)L * n4, hipMemcpyDeviceToHost));
-  p += (size_t)L * n4;
+  if (c->sm) HIP_TRY(c, hipMemcpy(p, c->rbq, (size_t)L * n4 * 2, hipMemcpyDeviceToHost));
+  else HIP_TRY(c, hipMemcpy(p, c->rb, (size_t)L * n4, hipMemcpyDeviceToHost));
+  p += (size_t)L * c->N * cell;
   if (n_pend > 0) HIP_TRY(c, hipMemcpy(p, c->list[c->cur], (size_t)n_pend * 4, hipMemcpyDeviceToHost));
   return SD_OK;
 }
@@ -1191,7 +1360,9 @@ sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
   if (hd.cfg_hash != config_hash(c->cfg) || hd.N != c->N || hd.L != c->cfg.ring_len)
     return fail(c, SD_EINVAL, "state was saved from a different configuration");
   const size_t n4 = (size_t)c->N * 4;
-  const size_t need = sizeof hd + 4 * n4 + (size_t)hd.L * n4 + (size_t)hd.n_pending * 4;
+  const size_t cell = c->sm ? 8 : 4;
+  const size_t need =
+      sizeof hd + 4 * n4 + (size_t)hd.L * c->N * cell + (size_t)hd.n_pending * 4;
   if (n < need || hd.n_pending < 0 || hd.n_pending > c->list_cap)
     return fail(c, SD_EINVAL, "state buffer holds %zu B, %zu needed", n, need);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1201,8 +1372,9 @@ sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
   HIP_TRY(c, hipMemcpy(c->y2, p + 2 * n4, n4, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->r, p + 3 * n4, n4, hipMemcpyHostToDevice));
   p += 4 * n4;
-  HIP_TRY(c, hipMemcpy(c->rb, p, (size_t)hd.L * n4, hipMemcpyHostToDevice));
-  p += (size_t)hd.L * n4;
+  if (c->sm) HIP_TRY(c, hipMemcpy(c->rbq, p, (size_t)hd.L * n4 * 2, hipMemcpyHostToDevice));
+  else HIP_TRY(c, hipMemcpy(c->rb, p, (size_t)hd.L * n4, hipMemcpyHostToDevice));
+  p += (size_t)hd.L * c->N * cell;
   // the open slice's list goes to list 0 with counter 0; counter 1 (the
   // next list's) must be zero
   c->cur = 0;
@@ -1281,6 +1453,56 @@ sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8
   if (!c || !h_row) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->sm) {
+    // source-major: segments are contiguous; their order is the fill's, so
+    // sort each by (target, delay, weight) for a canonical export
+    std::vector<unsigned long long> rp((size_t)c->M);
+    HIP_TRY(c, hipMemcpy(rp.data(), c->row64, (size_t)c->M * 8, hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s <= c->n_src; ++s) h_row[s] = (int64_t)rp[(size_t)s];
+    if (!h_tgt && !h_dly && !h_w) return SD_OK;
+    const sd_config& g = c->cfg;
+    const bool f32 = g.wform == SD_W_FP32;
+    std::vector<uint32_t> td((size_t)c->n_syn);
+    std::vector<uint8_t> wb((size_t)c->n_syn * (f32 ? 4 : 2));
+    if (c->n_syn) {
+      HIP_TRY(c, hipMemcpy(td.data(), c->tgtd, td.size() * 4, hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy(wb.data(), c->wbits, wb.size(), hipMemcpyDeviceToHost));
+    }
+    struct Ent { int32_t t; uint8_t d; float w; };
+    std::vector<Ent> seg;
+    for (int64_t s = 0; s < c->n_src; ++s) {
+      const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
+      seg.clear();
+      for (int64_t e = h_row[s]; e < h_row[s + 1]; ++e) {
+        Ent x;
+        x.t = (int32_t)(td[(size_t)e] & ((1u << kTgtBits) - 1));
+        x.d = (uint8_t)(g.d_min + (int)(td[(size_t)e] >> kTgtBits));
+        if (f32) {
+          std::memcpy(&x.w, wb.data() + (size_t)e * 4, 4);
+        } else {
+          uint16_t h;
+          std::memcpy(&h, wb.data() + (size_t)e * 2, 2);
+          const uint32_t u = (uint32_t)h << 16;
+          float d;
+          std::memcpy(&d, &u, 4);
+          x.w = g.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
+        }
+        seg.push_back(x);
+      }
+      std::sort(seg.begin(), seg.end(), [](const Ent& a, const Ent& b) {
+        if (a.t != b.t) return a.t < b.t;
+        if (a.d != b.d) return a.d < b.d;
+        return a.w < b.w;
+      });
+      for (size_t i = 0; i < seg.size(); ++i) {
+        const int64_t at = h_row[s] + (int64_t)i;
+        if (h_tgt) h_tgt[at] = seg[i].t;
+        if (h_dly) h_dly[at] = seg[i].d;
+        if (h_w) h_w[at] = seg[i].w;
+      }
+    }
+    return SD_OK;
+  }
   std::vector<uint32_t> rp((size_t)c->M);
   HIP_TRY(c, hipMemcpy(rp.data(), c->row, (size_t)c->M * 4, hipMemcpyDeviceToHost));
   const int64_t S = c->n_src;
@@ -1320,6 +1542,7 @@ sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8
 sd_status sd_export_segments(sd_ctx* c, int64_t src, int64_t* h_start, int64_t* h_len) {
   if (!c || !h_start || !h_len || src < 0 || src >= c->n_src) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  if (c->sm) return fail(c, SD_EUNSUPPORTED, "source-major layout has no per-block segments");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int32_t b = 0; b < c->NB; ++b) {
     uint32_t p[2];
@@ -1369,6 +1592,7 @@ sd_status sd_export_block(sd_ctx* c, int32_t b, int64_t* h_row, int32_t* h_tgt, 
                           float* h_w, int64_t* n_out) {
   if (!c || !h_row || b < 0 || b >= c->NB) return SD_EINVAL;
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  if (c->sm) return fail(c, SD_EUNSUPPORTED, "source-major layout has no block regions");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const int64_t S = c->n_src;
   std::vector<uint32_t> rp((size_t)S + 1);
@@ -1443,6 +1667,9 @@ sd_status sd_batch_create(const sd_config* cfgs, int32_t n, void* hip_stream, sd
       return bfail(bt, st, m);
     }
     bt->nets.push_back(c);
+    if (c->sm)
+      return bfail(bt, SD_EUNSUPPORTED, "member " + std::to_string(i) +
+                                            ": batches hold block-major networks only");
     for (int32_t b = 0; b < c->NB; ++b) blocks.push_back(make_int2(i, b));
     lds = std::max(lds, slice_lds_bytes(c->B, cfgs[i].d_min, cfgs[i].d_max));
   }

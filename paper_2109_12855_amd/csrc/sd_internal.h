@@ -37,6 +37,7 @@ struct SliceArgs {
   int32_t NB, B;           // blocks, neurons per block
   int32_t K;               // in-degree: block b's synapses start at b * B * K
   int32_t Dmin, Dmax, L;
+  int32_t win_rows;        // rows of the LDS window (Dmax; 0: no LDS delivery)
   int64_t src_e_end;       // source ids below this are excitatory
   // fixed-point weight of a synapse: trunc(m1 * x + m0) with x the decoded
   // BF16 residual (residual forms) or the weight itself (FP32, BF16); the
@@ -65,8 +66,10 @@ struct SliceArgs {
   float e_l, v_th, v_reset, drive_w;
   int32_t ref_steps;
   int32_t model;
-  // ring buffer [L][N]
+  // ring buffer [L][N]: FP32 (block-major layout) or 64-bit fixed point
+  // (source-major layout, rbq non-null; then there is no LDS delivery)
   float* rb;
+  const long long* rbq;
   int64_t rb_hi;           // rows of steps in [., rb_hi) hold valid sums
   // new spikes
   int32_t write_list;      // closed loop: feed spikes back
@@ -93,6 +96,11 @@ struct BuildArgs {
   uint32_t* row;           // counts, then exclusive scan (block-major)
   uint32_t* cursor;        // fill cursors (copy of row)
   uint2* seg;              // source-major (start, count) pairs
+  // source-major layout
+  unsigned long long* row64;     // counts, then exclusive scan, per source
+  unsigned long long* cursor64;  // fill cursors
+  uint32_t* tgtd;                // target | (delay - d_min) << 26
+  void* wbits;                   // u16 BF16 / residual bits, or f32 weight
   void* syn;
   uint8_t* syn_dly;
   int32_t wform;
@@ -103,6 +111,29 @@ struct BuildArgs {
   uint32_t fix_bits_e, fix_bits_i;
   int32_t fixed;
 };
+
+// Delivery in the source-major layout: every spike's segment is walked and
+// each weight added into the 64-bit fixed-point ring with a global atomic.
+struct SmDeliverArgs {
+  const unsigned long long* row;  // [n_src + 1]
+  const uint32_t* tgtd;
+  const void* wbits;
+  int32_t wform;
+  const uint32_t* in_list;        // (src << 5 | lag)
+  const int32_t* in_cnt;
+  int64_t in_cap;
+  int64_t n_src;
+  long long* ring;                // [L][N]
+  int64_t N;
+  int32_t L, Dmin;
+  int64_t t0;                     // first step of the spikes' slice
+  int64_t src_e_end;
+  float wm0_e, wm1_e, wm0_i, wm1_i;
+  unsigned long long* ev_count;
+  unsigned long long* spk_in_count;
+  int32_t* overflow;
+};
+constexpr int kTgtBits = 26;
 
 // launch wrappers (sd_kernels.hip)
 hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,
@@ -117,7 +148,14 @@ hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a);
 // one fused slice: workgroup gx serves block map[gx].y of network map[gx].x
 hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_map,
                         int32_t n_blocks, size_t lds, int wform);
-size_t slice_lds_bytes(int B, int Dmin, int Dmax);
+size_t slice_lds_bytes(int B, int Dmin, int win_rows);
+hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a);
+hipError_t launch_scan64(hipStream_t s, unsigned long long* data, int64_t n,
+                         unsigned long long* tile_sums, int64_t n_tiles_cap);
+hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a);
+hipError_t launch_deliver_sm(hipStream_t s, const SmDeliverArgs& a);
+hipError_t launch_zero_rows64(hipStream_t s, long long* rb, int64_t N, int32_t L, int64_t t_lo,
+                              int64_t t_hi);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);
 hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,

@@ -174,45 +174,48 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T& total) {
   return res;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* data, int64_t n,
-                                                            uint32_t* tile_sums) {
-  __shared__ uint32_t sh[kScanThreads / 64 + 1];
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const T* data, int64_t n,
+                                                            T* tile_sums) {
+  __shared__ T sh[kScanThreads / 64 + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  uint32_t s = 0;
+  T s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i)
     if (base + i < n) s += data[base + i];
-  uint32_t tot;
-  block_excl_scan<uint32_t>(s, sh, tot);
+  T tot;
+  block_excl_scan<T>(s, sh, tot);
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* tile_sums, int64_t n_tiles) {
-  __shared__ uint32_t sh[kScanThreads / 64 + 1];
-  uint32_t carry = 0;
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(T* tile_sums, int64_t n_tiles) {
+  __shared__ T sh[kScanThreads / 64 + 1];
+  T carry = 0;
   for (int64_t c0 = 0; c0 < n_tiles; c0 += kScanThreads) {
     const int64_t i = c0 + threadIdx.x;
-    const uint32_t v = i < n_tiles ? tile_sums[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<uint32_t>(v, sh, tot);
+    const T v = i < n_tiles ? tile_sums[i] : (T)0;
+    T tot;
+    const T ex = block_excl_scan<T>(v, sh, tot);
     if (i < n_tiles) tile_sums[i] = carry + ex;
     carry += tot;
   }
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply(uint32_t* data, int64_t n,
-                                                            const uint32_t* tile_sums) {
-  __shared__ uint32_t sh[kScanThreads / 64 + 1];
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(T* data, int64_t n,
+                                                            const T* tile_sums) {
+  __shared__ T sh[kScanThreads / 64 + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  uint32_t v[kScanPer];
-  uint32_t s = 0;
+  T v[kScanPer];
+  T s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    v[i] = (base + i < n) ? data[base + i] : 0u;
+    v[i] = (base + i < n) ? data[base + i] : (T)0;
     s += v[i];
   }
-  uint32_t tot;
-  uint32_t run = block_excl_scan<uint32_t>(s, sh, tot) + tile_sums[blockIdx.x];
+  T tot;
+  T run = block_excl_scan<T>(s, sh, tot) + tile_sums[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
     if (base + i < n) data[base + i] = run;
@@ -317,6 +320,102 @@ __global__ void k_seg_pairs(const uint32_t* row, int64_t n_src, int32_t NB, uint
   seg[i] = make_uint2(lo, row[b * n_src + s + 1] - lo);
 }
 
+// Source-major layout: per-source histogram, then a fill that appends each
+// synapse to its source's segment through a per-source cursor.  The order
+// inside a segment depends on atomic timing; delivery sums are exact
+// integers, so results do not, and exports sort segments canonically.
+__global__ void __launch_bounds__(256) k_count_sm(BuildArgs a) {
+  const int64_t j = blockIdx.x;
+  for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
+    const Draw d = draw_synapse(a, j, k);
+    atomicAdd(&a.row64[d.src], 1ull);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
+  const int64_t j = blockIdx.x;
+  for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
+    const Draw d = draw_synapse(a, j, k);
+    const unsigned long long pos = atomicAdd(&a.cursor64[d.src], 1ull);
+    a.tgtd[pos] = (uint32_t)j | ((uint32_t)(d.dly - a.d_min) << kTgtBits);
+    if (a.wform == WF_FP32) {
+      float w;
+      if (a.fixed) w = d.inh ? a.w_fix_i : a.w_fix_e;
+      else w = d.inh ? ((const float*)a.wtab_i)[d.widx] : ((const float*)a.wtab_e)[d.widx];
+      ((float*)a.wbits)[pos] = w;
+    } else {
+      uint32_t wb;
+      if (a.fixed) wb = d.inh ? a.fix_bits_i : a.fix_bits_e;
+      else wb = d.inh ? ((const uint16_t*)a.wtab_i)[d.widx] : ((const uint16_t*)a.wtab_e)[d.widx];
+      ((uint16_t*)a.wbits)[pos] = (uint16_t)wb;
+    }
+  }
+}
+
+// Source-major delivery: each wave takes spikes (grid-stride), walks the
+// spike's contiguous segment with coalesced loads, kUnrollSm elements per
+// lane in flight, and adds trunc(m1 * x + m0) into ring[(t0 + d_min + lag +
+// delay - d_min) % L][target] with a 64-bit global atomic (exact sums).
+constexpr int kSmThreads = 256;
+constexpr int kUnrollSm = 4;
+__global__ void __launch_bounds__(kSmThreads) k_deliver_sm(SmDeliverArgs a) {
+  __shared__ unsigned long long s_ev;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid == 0) s_ev = 0;
+  __syncthreads();
+  int64_t total = (int64_t)*a.in_cnt;
+  if (total > a.in_cap) total = a.in_cap;
+  const int64_t nw = (int64_t)gridDim.x * (kSmThreads / 64);
+  const int64_t gw = (int64_t)blockIdx.x * (kSmThreads / 64) + __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool fp32 = a.wform == WF_FP32;
+  uint64_t ev = 0;
+  for (int64_t i = gw; i < total; i += nw) {
+    const uint32_t ent = __builtin_amdgcn_readfirstlane(a.in_list[i]);
+    const uint32_t src = ent >> 5;
+    const int lag = (int)(ent & 31u);
+    if (lag >= a.Dmin || (int64_t)src >= a.n_src) {
+      if (lane == 0) atomicOr(a.overflow, 4);
+      continue;
+    }
+    const unsigned long long lo = a.row[src], hi = a.row[src + 1];
+    ev += hi - lo;
+    const bool inh = (int64_t)src >= a.src_e_end;
+    const float m0 = inh ? a.wm0_i : a.wm0_e, m1 = inh ? a.wm1_i : a.wm1_e;
+    const int base_row = (int)((a.t0 + a.Dmin + lag) % a.L);
+    for (unsigned long long e0 = lo; e0 < hi; e0 += 64 * kUnrollSm) {
+      uint32_t td[kUnrollSm];
+      float x[kUnrollSm];
+#pragma unroll
+      for (int u = 0; u < kUnrollSm; ++u) {
+        const unsigned long long e = e0 + (unsigned long long)(u * 64 + lane);
+        const unsigned long long ec = e < hi ? e : lo;  // in bounds (lo < hi here)
+        td[u] = a.tgtd[ec];
+        x[u] = fp32 ? ((const float*)a.wbits)[ec]
+                    : __uint_as_float((uint32_t)((const uint16_t*)a.wbits)[ec] << 16);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnrollSm; ++u) {
+        const unsigned long long e = e0 + (unsigned long long)(u * 64 + lane);
+        if (e < hi) {
+          int row = base_row + (int)(td[u] >> kTgtBits);
+          if (row >= a.L) row -= a.L;
+          const int64_t cell = (int64_t)row * a.N + (int64_t)(td[u] & ((1u << kTgtBits) - 1));
+          const long long v = (long long)(int)fmaf(m1, x[u], m0);
+          atomicAdd((unsigned long long*)&a.ring[cell], (unsigned long long)v);
+        }
+      }
+    }
+  }
+  if (lane == 0 && ev)
+    __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  __syncthreads();
+  if (tid == 0) {
+    if (s_ev) atomicAdd(a.ev_count, s_ev);
+    if (blockIdx.x == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the fused slice kernel
 // ---------------------------------------------------------------------------
@@ -389,11 +488,11 @@ __device__ __forceinline__ float from_fixed(long long q, double inv) {
 struct SliceLds {
   size_t win, carry, dcnt, mask, thr, scr, desc, meta, total;
 };
-__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax) {
+__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_rows) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   SliceLds L;
   size_t o = 0;
-  L.win = o;   o = up(o + (size_t)Dmax * B * 8);        // int64 ring window
+  L.win = o;   o = up(o + (size_t)win_rows * B * 8);    // int64 ring window
   L.carry = o; o = up(o + (size_t)Dmin * B * 4);        // staged HBM rows (FP32)
   L.dcnt = o;  o = up(o + (size_t)Dmin * B);            // Poisson-drive counts (u8)
   L.mask = o;  o = up(o + (size_t)Dmin * (B / 32) * 4); // spike bitmask
@@ -407,7 +506,9 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int Dmax) 
   return L;
 }
 
-size_t slice_lds_bytes(int B, int Dmin, int Dmax) { return slice_lds_layout(B, Dmin, Dmax).total; }
+size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
+  return slice_lds_layout(B, Dmin, win_rows).total;
+}
 
 // One workgroup's slice for target block b of the network described by a.
 template <int WF>
@@ -423,7 +524,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   const int Wd = B >> 5;
   const int Dmin = a.Dmin;
 
-  const SliceLds Lo = slice_lds_layout(B, Dmin, a.Dmax);
+  const SliceLds Lo = slice_lds_layout(B, Dmin, a.win_rows);
   long long* win = (long long*)(lds_raw + Lo.win);
   float* carry = (float*)(lds_raw + Lo.carry);
   uint8_t* dcnt = lds_raw + Lo.dcnt;
@@ -475,7 +576,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     for (int q = 0; q < kRows; ++q) {
       int rr = r0 + (q < rows ? q : 0);
       if (rr >= a.L) rr -= a.L;
-      stage[q] = a.rb[(int64_t)rr * a.N + j0 + n_own];
+      const int64_t at = (int64_t)rr * a.N + j0 + n_own;
+      stage[q] = a.rbq ? from_fixed(a.rbq[at], a.fx_inv) : a.rb[at];
     }
   }
   float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
@@ -664,7 +766,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         const int q = i / nb, n = i - q * nb;
         int rr = r0 + q;
         while (rr >= a.L) rr -= a.L;
-        carry[q * B + n] = a.rb[(int64_t)rr * a.N + j0 + n];
+        const int64_t at = (int64_t)rr * a.N + j0 + n;
+        carry[q * B + n] = a.rbq ? from_fixed(a.rbq[at], a.fx_inv) : a.rb[at];
       }
     }
     // rows at or past rb_hi hold no earlier input
@@ -845,6 +948,14 @@ __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64
   rb[(t % L) * N + (i % N)] = 0.f;
 }
 
+__global__ void k_zero_rows64(long long* rb, int64_t N, int32_t L, int64_t t_lo, int64_t t_hi) {
+  const int64_t rows = t_hi - t_lo;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * N) return;
+  const int64_t t = t_lo + i / N;
+  rb[(t % L) * N + (i % N)] = 0;
+}
+
 __device__ __forceinline__ uint32_t half32(const uint64_t w[4], int64_t t) {
   const uint64_t x = w[(t & 7) >> 1];
   return (t & 1) ? (uint32_t)(x >> 32) : (uint32_t)x;
@@ -913,15 +1024,49 @@ hipError_t launch_count(hipStream_t s, const BuildArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_sums,
-                       int64_t n_tiles_cap) {
+template <typename T>
+hipError_t scan_impl(hipStream_t s, T* data, int64_t n, T* tile_sums, int64_t n_tiles_cap) {
   const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
   if (n_tiles > n_tiles_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
+  hipLaunchKernelGGL(k_scan_tiles<T>, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
                      tile_sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sums, n_tiles);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
+  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(kScanThreads), 0, s, tile_sums, n_tiles);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, s, data, n,
                      tile_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_sums,
+                       int64_t n_tiles_cap) {
+  return scan_impl<uint32_t>(s, data, n, tile_sums, n_tiles_cap);
+}
+
+hipError_t launch_scan64(hipStream_t s, unsigned long long* data, int64_t n,
+                         unsigned long long* tile_sums, int64_t n_tiles_cap) {
+  return scan_impl<unsigned long long>(s, data, n, tile_sums, n_tiles_cap);
+}
+
+hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a) {
+  hipLaunchKernelGGL(k_count_sm, dim3((unsigned)a.N), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a) {
+  hipLaunchKernelGGL(k_fill_sm, dim3((unsigned)a.N), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_deliver_sm(hipStream_t s, const SmDeliverArgs& a) {
+  hipLaunchKernelGGL(k_deliver_sm, dim3(2048), dim3(kSmThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_rows64(hipStream_t s, long long* rb, int64_t N, int32_t L, int64_t t_lo,
+                              int64_t t_hi) {
+  if (t_hi <= t_lo) return hipSuccess;
+  const int64_t n = (t_hi - t_lo) * N;
+  hipLaunchKernelGGL(k_zero_rows64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rb, N, L,
+                     t_lo, t_hi);
   return hipGetLastError();
 }
 

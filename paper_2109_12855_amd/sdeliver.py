@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "SD_OK", -1: "SD_EINVAL", -2: "SD_ENOMEM", -3: "SD_EHIP", -4:
                 -5: "SD_ESTATE", -6: "SD_EUNSUPPORTED"}
 SD_IAF_PSC_DELTA, SD_IAF_PSC_ALPHA = 0, 1
 SD_W_FP32, SD_W_BF16, SD_W_BF16_RESID, SD_W_BF16_PACKED = 0, 1, 2, 3
+SD_LAYOUT_AUTO, SD_LAYOUT_BLOCK, SD_LAYOUT_SOURCE = 0, 1, 2
 
 
 class SdError(RuntimeError):
@@ -49,6 +50,7 @@ class sd_config(C.Structure):
         ("block_neurons", C.c_int32),
         ("record_spikes", C.c_int32),
         ("record_cap", C.c_int64),
+        ("layout", C.c_int32),
     ]
 
 
@@ -58,6 +60,7 @@ class sd_sizes(C.Structure):
         ("block_neurons", C.c_int32), ("n_blocks", C.c_int32),
         ("table_bytes", C.c_int64), ("arena_bytes", C.c_int64),
         ("bytes_per_synapse", C.c_int32),
+        ("layout", C.c_int32),
     ]
 
 

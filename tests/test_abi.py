@@ -89,7 +89,9 @@ def test_sizes_of_workloads():
     (dict(n_exc=0, n_inh=0), sdeliver.SD_EINVAL),
     (dict(block_neurons=100), sdeliver.SD_EINVAL),
     (dict(tau_syn=10.0), sdeliver.SD_EINVAL),    # tau_s == tau_m singularity
-    (dict(block_neurons=8192), sdeliver.SD_EUNSUPPORTED),  # window > LDS
+    (dict(block_neurons=8192, layout=1), sdeliver.SD_EUNSUPPORTED),  # window > LDS
+    (dict(layout=3), sdeliver.SD_EINVAL),
+    (dict(block_neurons=2048, layout=2), sdeliver.SD_EINVAL),  # > 1 neuron per thread
 ])
 def test_invalid_configs_rejected(over, code):
     with pytest.raises(sdeliver.SdError) as e:
@@ -97,7 +99,23 @@ def test_invalid_configs_rejected(over, code):
     assert e.value.status == code
 
 
-def test_brain_share_needs_sparse_layout():
+def test_brain_share_takes_source_major_layout():
+    """1.27e10 synapses from 10M virtual sources: beyond the block-major
+    layout's 32-bit pointers, so the automatic choice is source-major."""
+    s = sdeliver.query_sizes(W.ALPHA_BRAIN_SHARE)
+    assert s["layout"] == sdeliver.SD_LAYOUT_SOURCE
+    assert s["n_syn"] == 1125000 * 11250
+    assert s["n_src"] == 10_000_000
+    assert s["bytes_per_synapse"] == 6
+    assert s["arena_bytes"] < 100 * 2**30
     with pytest.raises(sdeliver.SdError) as e:
-        sdeliver.query_sizes(W.ALPHA_BRAIN_SHARE)
+        sdeliver.query_sizes(W.ALPHA_BRAIN_SHARE, layout=1)
     assert e.value.status == sdeliver.SD_EUNSUPPORTED
+
+
+def test_layout_choice():
+    assert sdeliver.query_sizes(W.ALPHA_112K)["layout"] == sdeliver.SD_LAYOUT_BLOCK
+    s = sdeliver.query_sizes(W.ALPHA_112K, layout=2)
+    assert s["layout"] == sdeliver.SD_LAYOUT_SOURCE
+    assert s["bytes_per_synapse"] == 8
+    assert sdeliver.query_sizes(W.ALPHA_112K_BF16, layout=2)["bytes_per_synapse"] == 6

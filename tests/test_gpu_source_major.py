@@ -1,0 +1,178 @@
+"""The source-major layout on the GPU: tables, delivery and dynamics against
+the oracle, identity with the block-major layout, and the one-GPU share of
+the brain-scale network (1.27e10 synapses) on a target sample.
+
+Both layouts add every weight into a 64-bit fixed-point window with the same
+quantum (exact integer sums), so one delivery gives identical rings in either
+layout; over a run the block-major layout rounds a step's input per
+delivering slice and the source-major one rounds the total once, so runs are
+identical where every step's input comes from one delivery.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_12855_amd import sdeliver
+from paper_2109_12855_amd import workloads as W
+
+from helpers import compare_rasters
+from test_gpu_parity import _dev, _replay_check, _tiny_cases
+
+pytestmark = pytest.mark.gpu
+
+SM = sdeliver.SD_LAYOUT_SOURCE
+
+
+def _sorted_segments(row, tgt, dly, w):
+    out = []
+    for s in range(len(row) - 1):
+        a, b = row[s], row[s + 1]
+        out.append(sorted(zip(tgt[a:b].tolist(), dly[a:b].tolist(),
+                              np.float32(w[a:b]).tolist())))
+    return out
+
+
+@pytest.mark.parametrize("case", [0, 2, 4])
+@pytest.mark.parametrize("wform", [0, 2, 3])
+def test_connections_match_oracle(case, wform):
+    cfg = dict(_tiny_cases()[case], wform=wform, layout=SM)
+    net = sdeliver.Net(cfg).build()
+    assert net.sizes["layout"] == SM
+    row, tgt, dly, w = net.connections()
+    ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[wform]))
+    orow, otgt, odly, ow = ref.source_major()
+    assert np.array_equal(row, orow)
+    assert _sorted_segments(row, tgt, dly, w) == _sorted_segments(orow, otgt, odly, ow)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_replay_delivery(case):
+    cfg = dict(_tiny_cases()[case], layout=SM)
+    n = cfg["n_exc"] + cfg["n_inh"]
+    src, lag = W.replay_spikes(n, max(1, n // 3), cfg["d_min"], seed=case)
+    _replay_check(cfg, src, lag)
+
+
+@pytest.mark.parametrize("case", [0, 1, 3])
+def test_closed_loop_tiny(case):
+    cfg = dict(_tiny_cases()[case], record_spikes=1, layout=SM)
+    net = sdeliver.Net(cfg).build()
+    net.simulate_steps(400)
+    st, idx = net.spikes()
+    assert len(st) > 10
+    t_bad, explained, info = compare_rasters(cfg, st, idx, 400, eps=1e-3)
+    assert t_bad is None or explained, (t_bad, info)
+
+
+def test_layouts_identical_dynamics():
+    """Delta net with one delay (every step's input comes from one delivery):
+    block-major and source-major runs are identical in spikes and state."""
+    res = []
+    for layout in (sdeliver.SD_LAYOUT_BLOCK, SM):
+        net = sdeliver.Net(dict(W.DELTA_SMALL, record_spikes=1, layout=layout)).build()
+        net.simulate_steps(1000)
+        st, idx = net.spikes()
+        res.append((st, idx, net.state(), net.stats()))
+        net.close()
+    (sa, ia, xa, ta), (sb, ib, xb, tb) = res
+    assert len(sa) > 0
+    assert np.array_equal(sa, sb) and np.array_equal(ia, ib)
+    for k in ("V", "r"):
+        assert np.array_equal(xa[k], xb[k]), k
+    for k in ("events_delivered", "spikes_delivered", "spikes_emitted"):
+        assert ta[k] == tb[k], k
+
+
+@pytest.mark.parametrize("cfg,n_spikes", [
+    (W.tiny(model=1, n=2111, k=300, seed=8, d_lo=10, d_hi=20), 700),
+    (dict(W.ALPHA_112K, wform=3), 900),
+    (dict(W.ALPHA_112K, wform=0), 900),
+])
+def test_layouts_identical_rings(cfg, n_spikes):
+    """One delivery (weights and counts) into a fresh ring: both layouts
+    hold the same exact fixed-point sums, rounded once, so every cell is
+    identical.  (Over a run, a step receiving from two slices is rounded
+    per part in the block-major layout and once in the source-major one.)"""
+    n = cfg["n_exc"] + cfg["n_inh"]
+    src, lag = W.replay_spikes(n, n_spikes, cfg["d_min"], seed=n_spikes)
+    rings = {}
+    for layout in (sdeliver.SD_LAYOUT_BLOCK, SM):
+        for count in (False, True):
+            net = sdeliver.Net(dict(cfg, layout=layout)).build()
+            net.set_count_mode(count)
+            net.deliver(*_dev(src, lag), 0)
+            rings[(layout, count)] = net.ring()
+            ev = net.stats()["events_delivered"]
+            net.close()
+            rings[(layout, count, "ev")] = ev
+    for count in (False, True):
+        a, b = rings[(sdeliver.SD_LAYOUT_BLOCK, count)], rings[(SM, count)]
+        assert np.array_equal(a, b), count
+        assert rings[(sdeliver.SD_LAYOUT_BLOCK, count, "ev")] == rings[(SM, count, "ev")]
+
+
+def _open_loop_small():
+    return dict(W.tiny(model=1, n=500, k=100, seed=21, d_lo=10, d_hi=20), n_src_exc=20000,
+                n_src_inh=5000, src_rate_hz=8.0, drive_rate_hz=0.0, w_exc=45.6 * 30,
+                record_spikes=1)
+
+
+@pytest.mark.parametrize("layout", [sdeliver.SD_LAYOUT_BLOCK, SM])
+def test_open_loop_against_oracle(layout):
+    cfg = dict(_open_loop_small(), layout=layout)
+    net = sdeliver.Net(cfg).build()
+    assert net.sizes["layout"] == layout
+    net.prepare_input(300)
+    net.simulate_steps(300)
+    st, idx = net.spikes()
+    assert len(st) > 5
+    t_bad, explained, info = compare_rasters(cfg, st, idx, 300, eps=1e-3)
+    assert t_bad is None or explained, (t_bad, info)
+
+
+@pytest.mark.parametrize("layout", [sdeliver.SD_LAYOUT_BLOCK, SM])
+def test_open_loop_counts_exact(layout):
+    """Count mode: the first input slice's arrivals per cell equal the
+    oracle's for the same virtual spikes."""
+    cfg = dict(_open_loop_small(), layout=layout)
+    net = sdeliver.Net(cfg).build()
+    net.set_count_mode(True)
+    net.prepare_input(20)
+    net.simulate_steps(10)   # slice 0 updated; its input is pending
+    net.deliver()            # ... delivered into the window [10, 30)
+    got = net.ring(20)
+    ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]]))
+    src, lag = oracle.open_loop_spikes(cfg, 0, 10)
+    ref.deliver(src, lag, 0)
+    L = cfg["ring_len"]
+    exp = ref.counts()[[(10 + s) % L for s in range(20)]]
+    assert np.array_equal(got.astype(np.int64), exp.astype(np.int64))
+    assert net.stats()["spikes_delivered"] == len(src)
+
+
+def test_brain_share_full_size_sample():
+    """The one-GPU share of the brain-scale net at full size (1,125,000
+    targets, 10M virtual sources, 1.27e10 synapses): one input slice in
+    count mode, compared cell by cell with the oracle on 448 targets."""
+    cfg = dict(W.ALPHA_BRAIN_SHARE)
+    net = sdeliver.Net(cfg).build()
+    assert net.n_syn == 1125000 * 11250
+    assert net.sizes["layout"] == SM
+    net.set_count_mode(True)
+    net.prepare_input(20)
+    net.simulate_steps(10)
+    net.deliver()
+    got = net.ring(20)
+    lo, hi = 517_000, 517_448
+    ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=lo, tgt_hi=hi))
+    src, lag = oracle.open_loop_spikes(cfg, 0, 10, cap=1 << 20)
+    assert 60_000 < len(src) < 100_000
+    ref.deliver(src, lag, 0)
+    L = cfg["ring_len"]
+    exp = ref.counts()[[(10 + s) % L for s in range(20)]]
+    assert np.array_equal(got[:, lo:hi].astype(np.int64), exp.astype(np.int64))
+    # every synapse of every input spike was delivered
+    out_w, out_deg = ref.out_weight()
+    st = net.stats()
+    assert st["spikes_delivered"] == len(src)
+    assert st["overflow"] == 0
