@@ -136,6 +136,52 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
     return out
 
 
+def brain_share(slices: int = 100, warmup: int = 20) -> dict:
+    """The one-GPU share of the brain-scale network (1,125,000 alpha
+    neurons, in-degree 11,250 from a 10M virtual population firing at 8 Hz,
+    1.27e10 synapses, residual-BF16 weights, source-major layout): open-loop
+    input precomputed outside the timed region, then timed slices."""
+    import torch
+
+    from paper_2109_12855_amd import sdeliver, workloads
+
+    cfg = dict(workloads.ALPHA_BRAIN_SHARE)
+    d_min = cfg["d_min"]
+    t0 = time.time()
+    net = sdeliver.Net(cfg).build()
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    net.prepare_input((warmup + slices + 2) * d_min)
+    net.simulate_steps(warmup * d_min)
+    torch.cuda.synchronize()
+    s0 = net.stats()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    net.simulate_steps(slices * d_min)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    s1 = net.stats()
+    events = s1["events_delivered"] - s0["events_delivered"]
+    spikes = s1["spikes_delivered"] - s0["spikes_delivered"]
+    n = net.n_local
+    b_syn = net.sizes["bytes_per_synapse"]
+    b_alg = algorithmic_bytes(events / slices, spikes / slices, n, d_min, b_syn, 16)
+    out = {"workload": "alpha_share_1125000_k11250_open_loop", "synapses": net.n_syn,
+           "layout": "source_major", "bytes_per_synapse": b_syn, "build_s": round(t_build, 2),
+           "slices": slices, "ms_per_slice": ms / slices, "events_per_slice": events / slices,
+           "spikes_per_slice": spikes / slices, "events_per_s": events / (ms * 1e-3),
+           "alg_gbs": b_alg / (ms / slices * 1e-3) / 1e9,
+           "local_rate_hz": (s1["spikes_emitted"] - s0["spikes_emitted"]) /
+                            (n * slices * d_min * cfg["h"] * 1e-3)}
+    out["roofline_frac"] = out["alg_gbs"] / HBM_PEAK_GBS
+    net.close()
+    del net
+    torch.cuda.empty_cache()
+    return out
+
+
 def ring_errors(base: dict, forms: list, n_spikes: int = 900, seed: int = 2021) -> dict:
     """Ring contents of each BF16 storage form against the FP32 form after
     delivering the same replay list (one slice's worth of spikes): normwise
@@ -205,6 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
+    ap.add_argument("--no-brain-share", action="store_true",
+                    help="skip the 1.27e10-synapse brain-scale share measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-vs-FP32 ring error report")
     ap.add_argument("--copy-probe", action="store_true",
@@ -233,6 +281,10 @@ def main():
         _log(json.dumps(res[f]))
     if args.copy_probe:
         copy_probe()
+    share = None
+    if not args.no_brain_share:
+        share = brain_share()
+        _log("brain share: " + json.dumps(share))
     prec = None
     if not args.no_precision:
         prec = ring_errors(dict(base, name="precision"),
@@ -270,6 +322,7 @@ def main():
         "achieved_alg_gbs": head["alg_gbs"],
         "forms": res,
         "precision": prec,
+        "brain_share": share,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
