@@ -133,6 +133,7 @@ struct SliceLauncher {
   int half = 0;
   int2* d_map = nullptr;        // workgroup -> (network, block)
   int32_t n_blocks = 0;
+  int32_t single_nb = 0;        // one network: launched by value (map unused)
   size_t lds = 0;
   int wform = 0;
 };
@@ -179,6 +180,13 @@ void launcher_free(SliceLauncher& L) {
 // Launch n_slices fused slices whose arguments are list[k * per + i].
 hipError_t launcher_run(SliceLauncher& L, hipStream_t s, const sd::SliceArgs* list,
                         int64_t n_slices) {
+  if (L.single_nb > 0) {  // one network: arguments by value, nothing to upload
+    for (int64_t k = 0; k < n_slices; ++k) {
+      const hipError_t e = sd::launch_slice1(s, list[k], L.lds, L.wform);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   for (int64_t k0 = 0; k0 < n_slices; k0 += L.cap) {
     const int64_t k = std::min<int64_t>(L.cap, n_slices - k0);
     const int h = L.half;
@@ -807,9 +815,10 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
-  std::vector<int2> blocks((size_t)c->NB);
-  for (int32_t b = 0; b < c->NB; ++b) blocks[(size_t)b] = make_int2(0, b);
-  HIP_TRY(c, launcher_init(c->lau, 1, 256, xcd_map(blocks), lds, g.wform));
+  c->lau.per = 1;
+  c->lau.lds = lds;
+  c->lau.wform = g.wform;
+  c->lau.single_nb = c->NB;
   return SD_OK;
 }
 

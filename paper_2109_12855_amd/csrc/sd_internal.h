@@ -145,9 +145,12 @@ hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_
                        int64_t n_tiles_cap);
 hipError_t launch_fill(hipStream_t s, const BuildArgs& a);
 hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a);
-// one fused slice: workgroup gx serves block map[gx].y of network map[gx].x
+// one fused slice of a batch: workgroup gx serves block map[gx].y of
+// network map[gx].x, arguments in device memory
 hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_map,
                         int32_t n_blocks, size_t lds, int wform);
+// one fused slice of a single network, arguments by value
+hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wform);
 size_t slice_lds_bytes(int B, int Dmin, int win_rows);
 hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a);
 hipError_t launch_scan64(hipStream_t s, unsigned long long* data, int64_t n,

@@ -511,7 +511,9 @@ size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
 }
 
 // One workgroup's slice for target block b of the network described by a.
-template <int WF>
+// FX: the HBM ring holds 64-bit fixed-point cells (source-major layout,
+// update only); otherwise FP32 cells.
+template <int WF, bool FX>
 __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tid = threadIdx.x;
@@ -577,7 +579,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       int rr = r0 + (q < rows ? q : 0);
       if (rr >= a.L) rr -= a.L;
       const int64_t at = (int64_t)rr * a.N + j0 + n_own;
-      stage[q] = a.rbq ? from_fixed(a.rbq[at], a.fx_inv) : a.rb[at];
+      if constexpr (FX) stage[q] = from_fixed(a.rbq[at], a.fx_inv);
+      else stage[q] = a.rb[at];
     }
   }
   float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
@@ -767,7 +770,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         int rr = r0 + q;
         while (rr >= a.L) rr -= a.L;
         const int64_t at = (int64_t)rr * a.N + j0 + n;
-        carry[q * B + n] = a.rbq ? from_fixed(a.rbq[at], a.fx_inv) : a.rb[at];
+        if constexpr (FX) carry[q * B + n] = from_fixed(a.rbq[at], a.fx_inv);
+        else carry[q * B + n] = a.rb[at];
       }
     }
     // rows at or past rb_hi hold no earlier input
@@ -934,7 +938,24 @@ __global__ void __launch_bounds__(kSliceThreads)
     k_slice(const SliceArgs* __restrict__ args, const int2* __restrict__ map) {
   const int2 m = map[blockIdx.x];
   if (m.x < 0) return;
-  slice_block<WF>(args[m.x], m.y);
+  slice_block<WF, false>(args[m.x], m.y);
+}
+
+// One network: the arguments travel by value in the kernel-argument segment
+// (read where used, through a pointer to that segment), and the block is
+// (gx & 7) * per_xcd + (gx >> 3).  This saves the dependent loads of the
+// batched form at the start of every wave.
+struct SingleArgs {
+  SliceArgs a;
+  int32_t per_xcd;
+};
+template <int WF, bool FX>
+__global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
+  const SingleArgs* p = (const SingleArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  const int gx = blockIdx.x;
+  const int b = (gx & 7) * p->per_xcd + (gx >> 3);
+  if (b >= p->a.NB) return;
+  slice_block<WF, FX>(p->a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1098,6 +1119,35 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_ma
       break;
     default:
       hipLaunchKernelGGL(k_slice<WF_BF16_RESID>, grid, block, lds, s, d_args, d_map);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wform) {
+  SingleArgs sa;
+  sa.a = a;
+  sa.per_xcd = (a.NB + 7) / 8;
+  const dim3 grid((unsigned)(8 * sa.per_xcd)), block(kSliceThreads);
+  if (a.rbq) {
+    // fixed-point ring: update only (the source-major delivery is its own
+    // kernel), so the record form does not matter
+    if (a.do_deliver) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_slice1<WF_FP32, true>), grid, block, lds, s, sa);
+    return hipGetLastError();
+  }
+  switch (wform) {
+    case WF_FP32:
+      hipLaunchKernelGGL((k_slice1<WF_FP32, false>), grid, block, lds, s, sa);
+      break;
+    case WF_BF16:
+      hipLaunchKernelGGL((k_slice1<WF_BF16, false>), grid, block, lds, s, sa);
+      break;
+    case WF_PACKED:
+      hipLaunchKernelGGL((k_slice1<WF_PACKED, false>), grid, block, lds, s, sa);
+      break;
+    default:
+      hipLaunchKernelGGL((k_slice1<WF_BF16_RESID, false>), grid, block, lds, s, sa);
       break;
   }
   return hipGetLastError();
