@@ -542,8 +542,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
 
   // loads whose latency the LDS zeroing below covers
   const uint32_t thr_v = (tid < kMaxThr && tid < a.n_thr) ? a.thr[tid] : 0xffffffffu;
-  int64_t total = a.do_deliver ? (int64_t)*a.in_cnt : 0;
-  if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
+  const int64_t total_raw = a.do_deliver ? (int64_t)*a.in_cnt : 0;
 
   // window rows cover steps [w_lo, w_lo + Dmax)
   const int64_t w_lo = a.w_lo;
@@ -629,6 +628,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // ---- deliver the completed slice into the LDS window (Alg. REF) -------
   if (tid < kMaxThr) thr[tid] = thr_v;
   if (a.do_deliver) {
+    // overflow beyond the list's capacity is flagged by its writer
+    const int64_t total = total_raw < a.in_cap ? total_raw : a.in_cap;
     __syncthreads();  // thr / zeroing visible
 
     // Spikes are taken in chunks of one per thread.  Each block starts at a
@@ -860,18 +861,35 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
 
   // ---- rows of the window due in later slices go to the HBM ring -------
   if (a.do_deliver) {
+    // rows [t_first, w_lo + Dmax): all window reads first, then the stores
+    // (adds into rows that already hold earlier deliveries)
+    constexpr int kFl = 8;
     const double inv = a.fx_inv;
-    const int64_t t_end = w_lo + a.Dmax;
     int64_t t_first = a.t_upd + a.n_upd;
     if (t_first < w_lo) t_first = w_lo;
-    for (int64_t t = t_first; t < t_end; ++t) {
-      const int q = (int)(t - w_lo);
-      float* rowp = a.rb + (t % a.L) * a.N + j0;
-      const bool add = t < a.rb_hi;
-      for (int n = tid; n < nb; n += kSliceThreads) {
-        const float v = from_fixed(win[q * B + n], inv);
-        if (add) rowp[n] += v;
-        else rowp[n] = v;
+    const int nrows = (int)(w_lo + a.Dmax - t_first);
+    const int q0 = (int)(t_first - w_lo);
+    const int row0 = (int)(t_first % a.L);
+    int64_t add_rows = a.rb_hi - t_first;  // leading rows that are added into
+    if (add_rows < 0) add_rows = 0;
+    if (add_rows > nrows) add_rows = nrows;
+    const int n_add = (int)add_rows;
+    for (int n = tid; n < nb; n += kSliceThreads) {
+      for (int k0 = 0; k0 < nrows; k0 += kFl) {
+        float v[kFl];
+#pragma unroll
+        for (int k = 0; k < kFl; ++k)
+          if (k0 + k < nrows) v[k] = from_fixed(win[(q0 + k0 + k) * B + n], inv);
+#pragma unroll
+        for (int k = 0; k < kFl; ++k) {
+          if (k0 + k < nrows) {
+            int row = row0 + k0 + k;
+            if (row >= a.L) row -= a.L;  // row0 < L and nrows <= Dmax < L
+            float* p = a.rb + (int64_t)row * a.N + j0 + n;
+            if (k0 + k < n_add) *p += v[k];
+            else *p = v[k];
+          }
+        }
       }
     }
   }
