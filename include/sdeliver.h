@@ -71,13 +71,16 @@ typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
  *                     whose sources each reach many targets per block.
  *   SD_LAYOUT_SOURCE  source-major: each source's synapses to all local
  *                     targets form one contiguous segment (as in the
- *                     paper's per-process table, Sec. 3.1); deliveries go
- *                     into a 64-bit fixed-point ring in device memory by
- *                     global integer atomics.  For tables beyond 2^32
- *                     synapses and sources whose segments are sparse across
- *                     blocks (the one-GPU share of a brain-scale network).
+ *                     paper's per-process table, Sec. 3.1).  A delivery
+ *                     first sorts the slice's events by target block into
+ *                     4-byte binned records (8 for FP32) held in device
+ *                     memory, then accumulates them in the same LDS ring
+ *                     windows.  For tables beyond 2^32 synapses and sources
+ *                     whose segments are sparse across blocks (the one-GPU
+ *                     share of a brain-scale network).
  *   SD_LAYOUT_AUTO    block-major when it fits, else source-major.
- * Both give the same sums (exact integers in the fixed-point window). */
+ * Both give the same rings and dynamics: a delivery's sums are exact
+ * integers in the fixed-point window, rounded to FP32 once per delivery. */
 typedef enum { SD_LAYOUT_AUTO = 0, SD_LAYOUT_BLOCK = 1, SD_LAYOUT_SOURCE = 2 } sd_layout;
 
 typedef enum {
@@ -109,6 +112,10 @@ typedef struct {
   int32_t record_spikes;     /* keep a device raster of emitted spikes (0/1)    */
   int64_t record_cap;        /* raster capacity in spikes (0 = automatic)       */
   int32_t layout;            /* sd_layout                                       */
+  int32_t bin_cap;           /* source-major: records per (target block,
+                                binning workgroup) region and slice, at most
+                                1024; events past it take a slower exact path
+                                (0 = from the expected rate)                   */
 } sd_config;
 
 typedef struct {

@@ -237,7 +237,12 @@ struct sd_ctx {
   unsigned long long* tiles64 = nullptr;
   uint32_t* tgtd = nullptr;              // target | (delay - d_min) << 26
   void* wbits = nullptr;                 // weights (u16 bits or f32)
-  long long* rbq = nullptr;              // 64-bit fixed-point ring [L][N]
+  void* bins = nullptr;                  // binned records [NB][bin_P][bin_cap]
+  uint32_t* bin_cnt = nullptr;           // records per region [NB][bin_P]
+  long long* spill = nullptr;            // full regions' events [d_max][N]
+  int32_t* spill_flag = nullptr;         // [NB]
+  int32_t bin_P = 0, bin_cap = 0, bin_U = 0;
+  size_t bin_lds = 0;
   uint32_t* tile_sums = nullptr;
   int64_t n_tiles = 0;
   void* syn = nullptr;          // synapse records
@@ -360,10 +365,26 @@ struct Layout {
   int32_t B, NB, rec_bytes, dly_bytes;
   int64_t list_cap;
   bool sm = false;  // source-major layout
+  int32_t bin_P = 0, bin_cap = 0, bin_U = 0;  // binning (source-major)
   size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
-      off_counters, off_overflow, total;
+      off_counters, off_overflow, off_bins, off_bcnt, off_spill, off_sflag, total;
 };
+
+constexpr size_t kLdsBudget = 160 * 1024;  // LDS of one gfx950 workgroup
+
+// Records per (block, binning workgroup) region: the expected count at the
+// configured source rate (open loop) or a nominal 20 Hz (closed loop), with
+// room for 6 standard deviations and a floor; fuller regions spill.
+int32_t auto_bin_cap(const sd_config& c, const Layout& L) {
+  const double rate = c.n_src_exc > 0 ? c.src_rate_hz : 20.0;
+  const double spikes = (double)L.n_src * rate * c.d_min * c.h * 1e-3;
+  const double per_src = L.n_src > 0 ? (double)L.n_syn / (double)L.n_src : 0.0;
+  const double e = spikes / kBinProducers * per_src / std::max<int32_t>(L.NB, 1);
+  double cap = 1.25 * e + 6.0 * std::sqrt(e) + 64.0;
+  int64_t k = ((int64_t)std::ceil(cap) + 63) / 64 * 64;
+  return (int32_t)std::min<int64_t>(1024, std::max<int64_t>(64, k));
+}
 
 // Block-major geometry and its limits (LDS window, u16/packed offsets,
 // buffer-resource range, 32-bit segment pointers).
@@ -422,14 +443,45 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
              "d_max - d_min < 64";
       return SD_EUNSUPPORTED;
     }
-    // blocks only organise the update: one thread per neuron
-    int64_t b = (L->N + 255) / 256;
-    b = std::max<int64_t>(64, std::min<int64_t>(1024, (b + 63) / 64 * 64));
-    L->B = c->block_neurons > 0 ? c->block_neurons : (int32_t)b;
-    L->NB = (int32_t)((L->N + L->B - 1) / L->B);
-    if (L->B > kSliceThreads) {
+    // The events are binned by target block and accumulated in the same LDS
+    // ring windows as the block-major layout: the largest block whose window
+    // fits the LDS and whose slots fit the binned record's 15 bits.
+    auto fits = [&](int64_t b) {
+      return slice_lds_bytes((int)b, c->d_min, c->d_max) + 64 <= kLdsBudget &&
+             (int64_t)c->d_max * b <= (1 << kBinSlotBits);
+    };
+    int64_t b = c->block_neurons;
+    if (b <= 0) {
+      b = std::min<int64_t>(kSliceThreads, (L->N + 63) / 64 * 64);
+      while (b > 64 && !fits(b)) b -= 64;
+    }
+    if (b > kSliceThreads) {
       *why = "source-major layout needs block_neurons <= 1024";
       return SD_EINVAL;
+    }
+    if (!fits(b)) {
+      *why = "source-major layout needs a ring window that fits the LDS and "
+             "d_max * block_neurons <= 32768";
+      return SD_EUNSUPPORTED;
+    }
+    L->B = (int32_t)b;
+    L->NB = (int32_t)((L->N + L->B - 1) / L->B);
+    L->bin_P = kBinProducers;
+    L->bin_cap = c->bin_cap > 0 ? c->bin_cap : auto_bin_cap(*c, *L);
+    if (L->bin_cap > 1024) {
+      *why = "bin_cap must be at most 1024";
+      return SD_EINVAL;
+    }
+    const bool w8 = c->wform == SD_W_FP32;
+    L->bin_U = 0;
+    for (int u = w8 ? 16 : kBinMaxU; u >= 4; u -= 4)
+      if (bin_lds_bytes(L->NB, u, w8) + 64 <= kLdsBudget) {
+        L->bin_U = u;
+        break;
+      }
+    if (L->bin_U == 0 || L->NB > 65535) {
+      *why = "too many target blocks for the binning pass's LDS counters";
+      return SD_EUNSUPPORTED;
     }
     L->M = L->n_src + 1;
     L->rec_bytes = 4;                                  // target | delay
@@ -461,7 +513,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_y1 = take((size_t)L->N * 4);
   L->off_y2 = take((size_t)L->N * 4);
   L->off_r = take((size_t)L->N * 4);
-  L->off_rb = take((size_t)c->ring_len * L->N * (L->sm ? 8 : 4));
+  L->off_rb = take((size_t)c->ring_len * L->N * 4);
   L->off_list0 = take((size_t)L->list_cap * 4);
   L->off_list1 = take((size_t)L->list_cap * 4);
   L->off_cnt = take(3 * 4);
@@ -473,6 +525,11 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_p32 = take(8 * 4);
   L->off_counters = take(8 * 8);
   L->off_overflow = take(4);
+  const size_t brec = c->wform == SD_W_FP32 ? 8 : 4;
+  L->off_bins = take(L->sm ? (size_t)L->NB * L->bin_P * L->bin_cap * brec : 0);
+  L->off_bcnt = take(L->sm ? (size_t)L->NB * L->bin_P * 4 : 0);
+  L->off_spill = take(L->sm ? (size_t)c->d_max * L->N * 8 : 0);
+  L->off_sflag = take(L->sm ? (size_t)L->NB * 4 : 0);
   L->total = o;
   sd_sizes& z = L->sz;
   z.n_local = L->N;
@@ -508,7 +565,15 @@ SliceArgs base_args(sd_ctx* c) {
   a.Dmin = g.d_min;
   a.Dmax = g.d_max;
   a.L = g.ring_len;
-  a.win_rows = c->sm ? 0 : g.d_max;
+  a.win_rows = g.d_max;
+  if (c->sm) {
+    a.bins = c->bins;
+    a.bin_cnt = c->bin_cnt;
+    a.bin_P = c->bin_P;
+    a.bin_cap = c->bin_cap;
+    a.spill = c->spill;
+    a.spill_flag = c->spill_flag;
+  }
   a.src_e_end = c->src_e_end;
   {
     // fixed-point weight trunc(m1 * x + m0): x is the weight (FP32, BF16) or
@@ -543,7 +608,6 @@ SliceArgs base_args(sd_ctx* c) {
   a.ref_steps = c->ref_steps;
   a.model = g.model;
   a.rb = c->rb;
-  a.rbq = c->rbq;
   a.rb_hi = c->rb_hi;
   a.write_list = open_loop(g) ? 0 : 1;
   a.out_cap = c->list_cap;
@@ -568,42 +632,41 @@ sd_status fill_gap(sd_ctx* c, int64_t w_lo) {
   return SD_OK;
 }
 
-// Source-major delivery of n entries of in_list (count on the device) whose
-// slice starts at step t0: rows of the window [t0 + d_min, t0 + d_min +
-// d_max) not yet claimed are zeroed, then the atomic delivery kernel adds
-// every synapse of every spike.
-sd_status sm_deliver(sd_ctx* c, const uint32_t* in_list, const int32_t* in_cnt, int64_t in_cap,
-                     int64_t t0) {
+// Source-major layout, first pass of a delivery: the events of the entries
+// of in_list (count on the device) are binned by target block; the slice
+// launch that follows accumulates them.
+sd_status bin_events(sd_ctx* c, const uint32_t* in_list, const int32_t* in_cnt, int64_t in_cap) {
   const sd_config& g = c->cfg;
-  const int64_t w_lo = t0 + g.d_min;
-  const int64_t lo = std::max(c->t_now, c->rb_hi);
-  HIP_TRY(c, launch_zero_rows64(c->stream, c->rbq, c->N, g.ring_len, lo, w_lo + g.d_max));
-  c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
   const SliceArgs b = base_args(c);
-  SmDeliverArgs a;
+  BinArgs a;
   std::memset(&a, 0, sizeof a);
   a.row = c->row64;
   a.tgtd = c->tgtd;
   a.wbits = c->wbits;
-  a.wform = g.wform;
   a.in_list = in_list;
   a.in_cnt = in_cnt;
   a.in_cap = in_cap;
   a.n_src = c->n_src;
-  a.ring = c->rbq;
   a.N = c->N;
-  a.L = g.ring_len;
+  a.B = c->B;
+  a.NB = c->NB;
   a.Dmin = g.d_min;
-  a.t0 = t0;
+  a.U = c->bin_U;
+  a.cap = c->bin_cap;
+  a.inv_B = 1.0f / (float)c->B;
   a.src_e_end = c->src_e_end;
   a.wm0_e = b.wm0_e;
   a.wm1_e = b.wm1_e;
   a.wm0_i = b.wm0_i;
   a.wm1_i = b.wm1_i;
+  a.bins = c->bins;
+  a.bin_cnt = c->bin_cnt;
+  a.spill = c->spill;
+  a.spill_flag = c->spill_flag;
   a.ev_count = c->counters + 0;
   a.spk_in_count = c->counters + 1;
   a.overflow = c->overflow;
-  HIP_TRY(c, launch_deliver_sm(c->stream, a));
+  HIP_TRY(c, launch_bin(c->stream, a, c->bin_P, c->bin_lds, g.wform == SD_W_FP32));
   return SD_OK;
 }
 
@@ -728,16 +791,21 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
     c->tiles64 = (unsigned long long*)(A + L.off_tiles);
     c->tgtd = (uint32_t*)(A + L.off_syn);
     c->wbits = A + L.off_dly;
-    c->rbq = (long long*)(A + L.off_rb);
-    c->rb = nullptr;
+    c->bins = A + L.off_bins;
+    c->bin_cnt = (uint32_t*)(A + L.off_bcnt);
+    c->spill = (long long*)(A + L.off_spill);
+    c->spill_flag = (int32_t*)(A + L.off_sflag);
+    c->bin_P = L.bin_P;
+    c->bin_cap = L.bin_cap;
+    c->bin_U = L.bin_U;
+    c->bin_lds = bin_lds_bytes(L.NB, L.bin_U, cfg->wform == SD_W_FP32);
     c->row = nullptr;
     c->cursor = nullptr;
     c->seg = nullptr;
     c->syn = nullptr;
     c->syn_dly = nullptr;
-  } else {
-    c->rb = (float*)(A + L.off_rb);
   }
+  c->rb = (float*)(A + L.off_rb);
   c->list[0] = (uint32_t*)(A + L.off_list0);
   c->list[1] = (uint32_t*)(A + L.off_list1);
   c->cnt3 = (int32_t*)(A + L.off_cnt);
@@ -811,10 +879,13 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, c->sm ? 0 : g.d_max);
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max);
   if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
+  if (c->sm && (size_t)lds_max < c->bin_lds + 64)
+    return fail(c, SD_EUNSUPPORTED, "binning pass needs %zu B of LDS, device allows %d",
+                c->bin_lds, lds_max);
   c->lau.per = 1;
   c->lau.lds = lds;
   c->lau.wform = g.wform;
@@ -889,7 +960,8 @@ sd_status sd_build_connections(sd_ctx* c) {
     HIP_TRY(c, hipMemcpyAsync(c->cursor64, c->row64, (size_t)c->M * 8, hipMemcpyDeviceToDevice,
                               c->stream));
     if (c->K > 0) HIP_TRY(c, launch_fill_sm(c->stream, a));
-    HIP_TRY(c, hipMemsetAsync(c->rbq, 0, (size_t)c->cfg.ring_len * c->N * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->spill, 0, (size_t)g.d_max * c->N * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->spill_flag, 0, (size_t)c->NB * 4, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     unsigned long long total = 0;
     HIP_TRY(c, hipMemcpy(&total, c->row64 + c->M - 1, 8, hipMemcpyDeviceToHost));
@@ -1031,29 +1103,13 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
     if (n == 0) a.do_deliver = 0;
   }
   const int64_t w_lo = t0 + g.d_min;
-  if (c->sm) {
-    sd_status s = SD_OK;
-    if (a.do_deliver) {
-      s = sm_deliver(c, a.in_list, a.in_cnt, a.in_cap, t0);
-    } else {
-      const int64_t lo = std::max(c->t_now, c->rb_hi);
-      HIP_TRY(c, launch_zero_rows64(c->stream, c->rbq, c->N, g.ring_len, lo, w_lo + g.d_max));
-      c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
-    }
-    if (packed) {
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      HIP_TRY(c, hipFree(packed));
-    }
-    if (s != SD_OK) return s;
-    if (own) c->pend_open = false;
-    return SD_OK;
-  }
   sd_status s = fill_gap(c, w_lo);
   if (s != SD_OK) return s;
   a.rb_hi = c->rb_hi;
   a.w_lo = w_lo;
   if (a.do_deliver) {
-    s = launch_slice_checked(c, a);
+    if (c->sm) s = bin_events(c, a.in_list, a.in_cnt, a.in_cap);
+    if (s == SD_OK) s = launch_slice_checked(c, a);
     if (s != SD_OK) return s;
   } else {
     // an empty list still defines the window rows as zero
@@ -1097,12 +1153,10 @@ sd_status next_fused_slice(sd_ctx* c, int32_t m, SliceArgs* out) {
   a.out_cnt = c->cnt3 + cn;
   a.zero_cnt = c->cnt3 + (cn + 1) % 3;
   if (deliver && c->sm) {
-    // source-major: the delivery is its own launch (issued now); the
-    // fused launch then only updates
-    sd_status s = sm_deliver(c, a.in_list, a.in_cnt, a.in_cap, c->pend_t0);
+    // source-major: the binning pass is its own launch (issued now), the
+    // fused launch accumulates its records
+    sd_status s = bin_events(c, a.in_list, a.in_cnt, a.in_cap);
     if (s != SD_OK) return s;
-    a.do_deliver = 0;
-    a.rb_hi = c->rb_hi;
   }
   if (deliver) c->rb_hi = std::max(c->rb_hi, a.w_lo + g.d_max);
   c->cur = nxt;
@@ -1144,8 +1198,8 @@ sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
     }
     const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);
     SliceArgs a;
-    // source-major: the delivery launch is issued inside next_fused_slice,
-    // so queued updates go first and this update right after it
+    // source-major: the binning launch is issued inside next_fused_slice,
+    // so queued slices go first and this slice right after it
     sd_status s = c->sm ? flush() : SD_OK;
     if (s == SD_OK) s = next_fused_slice(c, m, &a);
     if (s != SD_OK) {
@@ -1236,14 +1290,7 @@ sd_status sd_read_ring(sd_ctx* c, float* h_out, int32_t n_slots) {
   for (int32_t s = 0; s < n_slots; ++s) {
     const int64_t t = c->t_now + s;
     float* dst = h_out + (size_t)s * c->N;
-    if (t < c->rb_hi && c->sm) {
-      // 64-bit fixed-point row, read out as the slice kernel does
-      std::vector<long long> q((size_t)c->N);
-      HIP_TRY(c, hipMemcpy(q.data(), c->rbq + (t % L) * c->N, (size_t)c->N * 8,
-                           hipMemcpyDeviceToHost));
-      const double inv = std::ldexp(1.0, -c->fx_shift);
-      for (int64_t n = 0; n < c->N; ++n) dst[n] = (float)((double)q[(size_t)n] * inv);
-    } else if (t < c->rb_hi) {
+    if (t < c->rb_hi) {
       HIP_TRY(c, hipMemcpy(dst, c->rb + (t % L) * c->N, (size_t)c->N * 4, hipMemcpyDeviceToHost));
     } else {
       std::memset(dst, 0, (size_t)c->N * 4);
@@ -1321,7 +1368,7 @@ sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
     HIP_TRY(c, hipMemcpy(&cnt, c->cnt3 + c->ci, 4, hipMemcpyDeviceToHost));
     n_pend = std::min<int64_t>(cnt, c->list_cap);
   }
-  const size_t cell = c->sm ? 8 : 4;  // fixed-point or FP32 ring cells
+  const size_t cell = 4;  // FP32 ring cells
   const size_t need = sizeof(StateHeader) + (size_t)c->N * 16 + (size_t)L * c->N * cell +
                       (size_t)n_pend * 4;
   *used = need;
@@ -1352,8 +1399,7 @@ sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
   HIP_TRY(c, hipMemcpy(p + 2 * n4, c->y2, n4, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(p + 3 * n4, c->r, n4, hipMemcpyDeviceToHost));
   p += 4 * n4;
-  if (c->sm) HIP_TRY(c, hipMemcpy(p, c->rbq, (size_t)L * n4 * 2, hipMemcpyDeviceToHost));
-  else HIP_TRY(c, hipMemcpy(p, c->rb, (size_t)L * n4, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(p, c->rb, (size_t)L * n4, hipMemcpyDeviceToHost));
   p += (size_t)L * c->N * cell;
   if (n_pend > 0) HIP_TRY(c, hipMemcpy(p, c->list[c->cur], (size_t)n_pend * 4, hipMemcpyDeviceToHost));
   return SD_OK;
@@ -1369,7 +1415,7 @@ sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
   if (hd.cfg_hash != config_hash(c->cfg) || hd.N != c->N || hd.L != c->cfg.ring_len)
     return fail(c, SD_EINVAL, "state was saved from a different configuration");
   const size_t n4 = (size_t)c->N * 4;
-  const size_t cell = c->sm ? 8 : 4;
+  const size_t cell = 4;
   const size_t need =
       sizeof hd + 4 * n4 + (size_t)hd.L * c->N * cell + (size_t)hd.n_pending * 4;
   if (n < need || hd.n_pending < 0 || hd.n_pending > c->list_cap)
@@ -1381,8 +1427,7 @@ sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
   HIP_TRY(c, hipMemcpy(c->y2, p + 2 * n4, n4, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->r, p + 3 * n4, n4, hipMemcpyHostToDevice));
   p += 4 * n4;
-  if (c->sm) HIP_TRY(c, hipMemcpy(c->rbq, p, (size_t)hd.L * n4 * 2, hipMemcpyHostToDevice));
-  else HIP_TRY(c, hipMemcpy(c->rb, p, (size_t)hd.L * n4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->rb, p, (size_t)hd.L * n4, hipMemcpyHostToDevice));
   p += (size_t)hd.L * c->N * cell;
   // the open slice's list goes to list 0 with counter 0; counter 1 (the
   // next list's) must be zero

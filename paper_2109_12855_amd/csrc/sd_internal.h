@@ -66,10 +66,18 @@ struct SliceArgs {
   float e_l, v_th, v_reset, drive_w;
   int32_t ref_steps;
   int32_t model;
-  // ring buffer [L][N]: FP32 (block-major layout) or 64-bit fixed point
-  // (source-major layout, rbq non-null; then there is no LDS delivery)
+  // source-major layout: the slice's events binned by target block (k_bin).
+  // Block b reads the bin_P regions [b * bin_P + p] of bin_cap records each,
+  // holding bin_cnt[b * bin_P + p] records; events past a full region were
+  // added into spill (64-bit fixed point, [Dmax][N] window rows), which block
+  // b consumes and clears when spill_flag[b] is set.  bins null: block-major.
+  const void* bins;
+  const uint32_t* bin_cnt;
+  int32_t bin_P, bin_cap;
+  long long* spill;
+  int32_t* spill_flag;
+  // ring buffer [L][N] (FP32)
   float* rb;
-  const long long* rbq;
   int64_t rb_hi;           // rows of steps in [., rb_hi) hold valid sums
   // new spikes
   int32_t write_list;      // closed loop: feed spikes back
@@ -112,27 +120,41 @@ struct BuildArgs {
   int32_t fixed;
 };
 
-// Delivery in the source-major layout: every spike's segment is walked and
-// each weight added into the 64-bit fixed-point ring with a global atomic.
-struct SmDeliverArgs {
-  const unsigned long long* row;  // [n_src + 1]
-  const uint32_t* tgtd;
-  const void* wbits;
-  int32_t wform;
+// Source-major delivery, pass 1: the events of a slice's spikes are sorted by
+// target block and written as binned records into per-(block, workgroup)
+// regions (record layout at kBinSlotBits).
+struct BinArgs {
+  const unsigned long long* row;  // [n_src + 1] segment starts
+  const uint32_t* tgtd;           // target | (delay - d_min) << kTgtBits
+  const void* wbits;              // u16 BF16 / residual bits, or f32 weight
   const uint32_t* in_list;        // (src << 5 | lag)
   const int32_t* in_cnt;
   int64_t in_cap;
-  int64_t n_src;
-  long long* ring;                // [L][N]
-  int64_t N;
-  int32_t L, Dmin;
-  int64_t t0;                     // first step of the spikes' slice
+  int64_t n_src, N;
+  int32_t B, NB, Dmin, U;         // U: events per thread per sorting chunk
+  int32_t cap;                    // records per region
+  float inv_B;                    // 1 / B (estimate of target / B)
   int64_t src_e_end;
-  float wm0_e, wm1_e, wm0_i, wm1_i;
+  float wm0_e, wm1_e, wm0_i, wm1_i;  // fixed-point weights of spilled events
+  void* bins;                     // [NB][P][cap] records
+  uint32_t* bin_cnt;              // [NB][P]
+  long long* spill;               // [Dmax][N]
+  int32_t* spill_flag;            // [NB]
   unsigned long long* ev_count;
   unsigned long long* spk_in_count;
   int32_t* overflow;
 };
+// Binned record: bits [0, 15) the window slot q * B + offset in block, where
+// q = lag + delay - d_min is the arrival step's row of the delivery window,
+// bit 15 the inhibitory flag, bits [16, 32) the BF16 weight or residual; the
+// FP32 form adds the f32 weight as a second word.
+constexpr int kBinSlotBits = 15;
+constexpr int kBinThreads = 1024;
+constexpr int kBinSpikes = 512;   // spikes resolved per descriptor batch
+constexpr int kBinMaxU = 20;      // events per thread per sorting chunk (4-byte records)
+constexpr int kBinProducers = 256;
+constexpr int kBinSlice = 256;    // records per consumer work item
+size_t bin_lds_bytes(int NB, int U, bool w8);
 constexpr int kTgtBits = 26;
 
 // launch wrappers (sd_kernels.hip)
@@ -156,9 +178,7 @@ hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a);
 hipError_t launch_scan64(hipStream_t s, unsigned long long* data, int64_t n,
                          unsigned long long* tile_sums, int64_t n_tiles_cap);
 hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a);
-hipError_t launch_deliver_sm(hipStream_t s, const SmDeliverArgs& a);
-hipError_t launch_zero_rows64(hipStream_t s, long long* rb, int64_t N, int32_t L, int64_t t_lo,
-                              int64_t t_hi);
+hipError_t launch_bin(hipStream_t s, const BinArgs& a, int32_t P, size_t lds, bool w8);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);
 hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,

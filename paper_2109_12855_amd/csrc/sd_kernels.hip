@@ -352,67 +352,253 @@ __global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
   }
 }
 
-// Source-major delivery: each wave takes spikes (grid-stride), walks the
-// spike's contiguous segment with coalesced loads, kUnrollSm elements per
-// lane in flight, and adds trunc(m1 * x + m0) into ring[(t0 + d_min + lag +
-// delay - d_min) % L][target] with a 64-bit global atomic (exact sums).
-constexpr int kSmThreads = 256;
-constexpr int kUnrollSm = 4;
-__global__ void __launch_bounds__(kSmThreads) k_deliver_sm(SmDeliverArgs a) {
-  __shared__ unsigned long long s_ev;
-  const int tid = threadIdx.x, lane = tid & 63;
-  if (tid == 0) s_ev = 0;
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// source-major delivery, pass 1: binning by target block
+// ---------------------------------------------------------------------------
+// In the one-GPU share of a brain-scale network a source reaches ~1 target
+// per block of B neurons, so per-(source, block) segments degenerate
+// (Sec. 3.2: segments shrink as the network is spread over more processes).
+// The slice's events are instead sorted by target block on the fly: each of
+// P workgroups takes a contiguous share of the spike list, walks the spikes'
+// segments (coalesced), and sorts chunks of U * 1024 events by block in LDS
+// (a returning LDS atomic on the block's counter gives an event's rank, a
+// block scan the bin starts).  Each bin's run is then appended to the
+// workgroup's own region of that block with coalesced stores, so no global
+// atomics are involved.  A region that fills up sends further events to the
+// fixed-point spill rows with global atomics and flags the block.
+struct BinLds {
+  size_t stage, cnt, cur, pre, lo, mt, scr, total;
+};
+__host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
+  auto up = [](size_t x) { return (x + 15) / 16 * 16; };
+  BinLds L;
+  size_t o = 0;
+  L.stage = o; o = up(o + (size_t)U * kBinThreads * (w8 ? 8 : 4));  // sorted chunk
+  L.cnt = o;   o = up(o + (size_t)(NB + 1) * 4);  // counts, then bin starts
+  L.cur = o;   o = up(o + (size_t)NB * 4);        // records in each region so far
+  L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per spike
+  L.lo = o;    o = up(o + (size_t)kBinSpikes * 8);  // segment start per spike
+  L.mt = o;    o = up(o + (size_t)kBinSpikes * 4);  // lag | inhibitory << 15
+  L.scr = o;   o = up(o + (size_t)(kBinThreads / 64 + 2) * 8);
+  L.total = o;
+  return L;
+}
+
+size_t bin_lds_bytes(int NB, int U, bool w8) { return bin_lds_layout(NB, U, w8).total; }
+
+template <bool W8>
+__global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
+  // fields are read where used, through a pointer to the kernel-argument
+  // segment (the whole struct in scalar registers would spill)
+  const BinArgs& a = *(const BinArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int nwv = kBinThreads / 64;
+  const int p = blockIdx.x, P = gridDim.x;
+  const int NB = a.NB, B = a.B, U = a.U, cap = a.cap;
+  const BinLds Lo = bin_lds_layout(NB, U, W8);
+  uint32_t* stage = (uint32_t*)(lds_raw + Lo.stage);
+  uint2* stage2 = (uint2*)(lds_raw + Lo.stage);
+  uint32_t* cnt = (uint32_t*)(lds_raw + Lo.cnt);
+  uint32_t* cur = (uint32_t*)(lds_raw + Lo.cur);
+  unsigned long long* pre = (unsigned long long*)(lds_raw + Lo.pre);
+  unsigned long long* lo = (unsigned long long*)(lds_raw + Lo.lo);
+  uint32_t* mt = (uint32_t*)(lds_raw + Lo.mt);
+  unsigned long long* scr64 = (unsigned long long*)(lds_raw + Lo.scr);
+  uint32_t* scr32 = (uint32_t*)(lds_raw + Lo.scr);
+
   int64_t total = (int64_t)*a.in_cnt;
-  if (total > a.in_cap) total = a.in_cap;
-  const int64_t nw = (int64_t)gridDim.x * (kSmThreads / 64);
-  const int64_t gw = (int64_t)blockIdx.x * (kSmThreads / 64) + __builtin_amdgcn_readfirstlane(tid >> 6);
-  const bool fp32 = a.wform == WF_FP32;
-  uint64_t ev = 0;
-  for (int64_t i = gw; i < total; i += nw) {
-    const uint32_t ent = __builtin_amdgcn_readfirstlane(a.in_list[i]);
-    const uint32_t src = ent >> 5;
-    const int lag = (int)(ent & 31u);
-    if (lag >= a.Dmin || (int64_t)src >= a.n_src) {
-      if (lane == 0) atomicOr(a.overflow, 4);
-      continue;
-    }
-    const unsigned long long lo = a.row[src], hi = a.row[src + 1];
-    ev += hi - lo;
-    const bool inh = (int64_t)src >= a.src_e_end;
-    const float m0 = inh ? a.wm0_i : a.wm0_e, m1 = inh ? a.wm1_i : a.wm1_e;
-    const int base_row = (int)((a.t0 + a.Dmin + lag) % a.L);
-    for (unsigned long long e0 = lo; e0 < hi; e0 += 64 * kUnrollSm) {
-      uint32_t td[kUnrollSm];
-      float x[kUnrollSm];
-#pragma unroll
-      for (int u = 0; u < kUnrollSm; ++u) {
-        const unsigned long long e = e0 + (unsigned long long)(u * 64 + lane);
-        const unsigned long long ec = e < hi ? e : lo;  // in bounds (lo < hi here)
-        td[u] = a.tgtd[ec];
-        x[u] = fp32 ? ((const float*)a.wbits)[ec]
-                    : __uint_as_float((uint32_t)((const uint16_t*)a.wbits)[ec] << 16);
+  if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
+  if (total < 0) total = 0;
+  const int64_t s_lo = total * p / P, s_hi = total * (p + 1) / P;
+  for (int i = tid; i <= NB; i += kBinThreads) cnt[i] = 0u;
+  for (int i = tid; i < NB; i += kBinThreads) cur[i] = 0u;
+  unsigned long long ev = 0;
+  const uint32_t tmask = (1u << kTgtBits) - 1u;
+  const size_t region0 = (size_t)p * cap;  // this workgroup's region in a block's area
+  const size_t area = (size_t)P * cap;     // records per block
+
+  for (int64_t sb = s_lo; sb < s_hi; sb += kBinSpikes) {
+    const int ns = (int)((s_hi - sb) < kBinSpikes ? (s_hi - sb) : kBinSpikes);
+    // (1) every thread resolves one spike into its segment
+    unsigned long long len = 0;
+    if (tid < ns) {
+      const uint32_t ent = a.in_list[sb + tid];
+      const uint32_t src = ent >> 5;
+      const uint32_t lag = ent & 31u;
+      unsigned long long l0 = 0;
+      if ((int)lag < a.Dmin && (int64_t)src < a.n_src) {
+        l0 = a.row[src];
+        len = a.row[src + 1] - l0;
+      } else {
+        atomicOr(a.overflow, 4);
       }
+      lo[tid] = l0;
+      mt[tid] = lag | (((int64_t)src >= a.src_e_end) ? 0x8000u : 0u);
+    }
+    unsigned long long n_batch;
+    const unsigned long long ex = block_excl_scan<unsigned long long>(len, scr64, n_batch);
+    if (tid < ns) pre[tid] = ex;
+    if (tid == 0) pre[ns] = n_batch;
+    ev += n_batch;  // the same value in every thread; thread 0 reports it
+    __syncthreads();
+
+    // (2) chunks of U * 1024 events of the batch, event f of the batch at
+    // thread f % 1024, slot f / 1024 (consecutive lanes read consecutive
+    // records of a segment)
+    const unsigned long long E_c = (unsigned long long)U * kBinThreads;
+    for (unsigned long long f0 = 0; f0 < n_batch; f0 += E_c) {
+      // spike of this thread's first event: the last one starting at or
+      // before it (pre[ns] = n_batch lies past every event)
+      int sp = 0;
+      {
+        const unsigned long long f = f0 + (unsigned long long)tid;
+        int l = 0, h = ns;
+        while (h - l > 1) {
+          const int m = (l + h) >> 1;
+          if (pre[m] <= f) l = m;
+          else h = m;
+        }
+        sp = l;
+      }
+      constexpr int UM = W8 ? 16 : kBinMaxU;  // register budget
+      const unsigned long long left = n_batch - f0;
+      const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
+      uint32_t key[UM], rec[UM], wrd[W8 ? UM : 1];
 #pragma unroll
-      for (int u = 0; u < kUnrollSm; ++u) {
-        const unsigned long long e = e0 + (unsigned long long)(u * 64 + lane);
-        if (e < hi) {
-          int row = base_row + (int)(td[u] >> kTgtBits);
-          if (row >= a.L) row -= a.L;
-          const int64_t cell = (int64_t)row * a.N + (int64_t)(td[u] & ((1u << kTgtBits) - 1));
-          const long long v = (long long)(int)fmaf(m1, x[u], m0);
-          atomicAdd((unsigned long long*)&a.ring[cell], (unsigned long long)v);
+      for (int u = 0; u < UM; ++u) key[u] = 0xffffffffu;  // no event
+#pragma unroll
+      for (int u0 = 0; u0 < UM; u0 += 4) {
+        if (u0 < U) {
+          uint32_t td[4], wb[4], m8[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t fr = (uint32_t)((u0 + k) * kBinThreads + tid);
+            td[k] = 0u;
+            wb[k] = 0u;
+            m8[k] = 0u;
+            if (fr < n_ev) {
+              const unsigned long long f = f0 + fr;
+              while (pre[sp + 1] <= f) ++sp;
+              const unsigned long long e = lo[sp] + (f - pre[sp]);
+              td[k] = a.tgtd[e];
+              if constexpr (W8) wb[k] = ((const uint32_t*)a.wbits)[e];
+              else wb[k] = ((const uint16_t*)a.wbits)[e];
+              m8[k] = mt[sp];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int u = u0 + k;
+            const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+            rec[u] = 0u;
+            if constexpr (W8) wrd[u] = wb[k];
+            if (fr < n_ev) {
+              const int tgt = (int)(td[k] & tmask);
+              // block = tgt / B from an FP32 estimate, corrected by one step
+              int blk = (int)((float)tgt * a.inv_B);
+              int off = tgt - blk * B;
+              if (off < 0) { --blk; off += B; }
+              if (off >= B) { ++blk; off -= B; }
+              const int q = (int)(m8[k] & 31u) + (int)(td[k] >> kTgtBits);
+              rec[u] = (uint32_t)(q * B + off) | (m8[k] & 0x8000u);
+              if constexpr (!W8) rec[u] |= wb[k] << 16;
+              const uint32_t rank = __hip_atomic_fetch_add(&cnt[blk], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+              key[u] = ((uint32_t)blk << 16) | rank;
+            }
+          }
         }
       }
+      __syncthreads();
+      // (3) bin starts: exclusive scan of the counts, in place
+      {
+        const int per = (NB + kBinThreads - 1) / kBinThreads;
+        const int i0 = tid * per, i1 = (i0 + per) < NB ? i0 + per : NB;
+        uint32_t sum = 0;
+        for (int i = i0; i < i1; ++i) sum += cnt[i];
+        uint32_t n_chunk;
+        uint32_t run = block_excl_scan<uint32_t>(sum, scr32, n_chunk);
+        for (int i = i0; i < i1; ++i) {
+          const uint32_t c = cnt[i];
+          cnt[i] = run;
+          run += c;
+        }
+        if (tid == 0) cnt[NB] = n_chunk;
+      }
+      __syncthreads();
+      // (4) scatter into bin order
+#pragma unroll
+      for (int u = 0; u < UM; ++u) {
+        if (key[u] != 0xffffffffu) {
+          const uint32_t at = cnt[key[u] >> 16] + (key[u] & 0xffffu);
+          if constexpr (W8) stage2[at] = make_uint2(rec[u], wrd[u]);
+          else stage[at] = rec[u];
+        }
+      }
+      __syncthreads();
+      // (5) append each bin's run to this workgroup's region of the block:
+      // a wave takes 64 blocks, lane l holding block g0 + l's start, count
+      // and fill; quarters of the wave then copy four blocks' runs at a time
+      // (runs of ~E_c / NB records: coalesced stores of that length)
+      for (int g0 = wv * 64; g0 < NB; g0 += nwv * 64) {
+        const int bl = g0 + lane;
+        uint32_t st = 0, n = 0, base = 0;
+        if (bl < NB) {
+          st = cnt[bl];
+          n = cnt[bl + 1] - st;
+          base = cur[bl];
+        }
+        const int sub = lane >> 4, sl = lane & 15;
+        for (int j = 0; j < 64; j += 4) {
+          const int lj = j + sub;
+          const uint32_t st_j = (uint32_t)__shfl((int)st, lj, 64);
+          const uint32_t n_j = (uint32_t)__shfl((int)n, lj, 64);
+          const uint32_t base_j = (uint32_t)__shfl((int)base, lj, 64);
+          const int b = g0 + lj;
+          for (uint32_t k = (uint32_t)sl; k < n_j; k += 16) {
+            const uint32_t pos = base_j + k;
+            if ((int)pos < cap) {
+              const size_t at = (size_t)b * area + region0 + pos;
+              if constexpr (W8) ((uint2*)a.bins)[at] = stage2[st_j + k];
+              else ((uint32_t*)a.bins)[at] = stage[st_j + k];
+            } else {
+              // region full: add the event's fixed-point weight into the
+              // spill rows with a global atomic
+              uint32_t r;
+              float w;
+              if constexpr (W8) {
+                const uint2 x = stage2[st_j + k];
+                r = x.x;
+                w = __uint_as_float(x.y);
+              } else {
+                r = stage[st_j + k];
+                w = __uint_as_float(r & 0xffff0000u);
+              }
+              const int slot = (int)(r & ((1u << kBinSlotBits) - 1u));
+              const int q = slot / B, off = slot - q * B;
+              const bool inh = (r & 0x8000u) != 0u;
+              const long long v =
+                  (long long)(int)fmaf(inh ? a.wm1_i : a.wm1_e, w, inh ? a.wm0_i : a.wm0_e);
+              atomicAdd((unsigned long long*)&a.spill[(int64_t)q * a.N + (int64_t)b * B + off],
+                        (unsigned long long)v);
+              a.spill_flag[b] = 1;
+            }
+          }
+        }
+        if (bl < NB) cur[bl] = base + n;
+      }
+      __syncthreads();
+      for (int i = tid; i <= NB; i += kBinThreads) cnt[i] = 0u;
+      __syncthreads();
     }
   }
-  if (lane == 0 && ev)
-    __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-  __syncthreads();
+  // record counts of this workgroup's regions
+  for (int b = tid; b < NB; b += kBinThreads)
+    a.bin_cnt[(size_t)b * P + p] = cur[b] < (uint32_t)cap ? cur[b] : (uint32_t)cap;
   if (tid == 0) {
-    if (s_ev) atomicAdd(a.ev_count, s_ev);
-    if (blockIdx.x == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+    if (ev) atomicAdd(a.ev_count, ev);
+    if (p == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
   }
 }
 
@@ -511,9 +697,10 @@ size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
 }
 
 // One workgroup's slice for target block b of the network described by a.
-// FX: the HBM ring holds 64-bit fixed-point cells (source-major layout,
-// update only); otherwise FP32 cells.
-template <int WF, bool FX>
+// BIN: the slice's events arrive binned by target block (source-major
+// layout, k_bin; WF_FP32 for 8-byte records, any other form for 4-byte
+// ones); otherwise they are read from the block-major segments.
+template <int WF, bool BIN>
 __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tid = threadIdx.x;
@@ -542,7 +729,15 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
 
   // loads whose latency the LDS zeroing below covers
   const uint32_t thr_v = (tid < kMaxThr && tid < a.n_thr) ? a.thr[tid] : 0xffffffffu;
-  const int64_t total_raw = a.do_deliver ? (int64_t)*a.in_cnt : 0;
+  const int64_t total_raw = (!BIN && a.do_deliver) ? (int64_t)*a.in_cnt : 0;
+  uint32_t bin_len = 0;
+  int spill_on = 0;
+  if constexpr (BIN) {
+    if (a.do_deliver) {
+      if (tid < a.bin_P) bin_len = a.bin_cnt[(size_t)b * a.bin_P + tid];
+      spill_on = a.spill_flag[b];
+    }
+  }
 
   // window rows cover steps [w_lo, w_lo + Dmax)
   const int64_t w_lo = a.w_lo;
@@ -578,8 +773,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       int rr = r0 + (q < rows ? q : 0);
       if (rr >= a.L) rr -= a.L;
       const int64_t at = (int64_t)rr * a.N + j0 + n_own;
-      if constexpr (FX) stage[q] = from_fixed(a.rbq[at], a.fx_inv);
-      else stage[q] = a.rb[at];
+      stage[q] = a.rb[at];
     }
   }
   float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
@@ -627,7 +821,97 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
 
   // ---- deliver the completed slice into the LDS window (Alg. REF) -------
   if (tid < kMaxThr) thr[tid] = thr_v;
-  if (a.do_deliver) {
+  if (BIN && a.do_deliver) {
+    __syncthreads();  // thr / zeroing visible
+    // Work items of up to kBinSlice records of one region of this block's
+    // bin area; waves take GB items at a time from a shared counter, RB
+    // records per lane each, all loads in flight before the adds (slots
+    // past a region's count load nothing: their buffer offset is out of
+    // range).  The record holds the window slot, so the adds need no
+    // per-item state.
+    constexpr bool W8 = WF == WF_FP32;
+    constexpr int GB = 4, RB = kBinSlice / 64;
+    int n_items;
+    const int n_it = (int)((bin_len + kBinSlice - 1) / kBinSlice);
+    const int it0 = block_excl_scan<int>(n_it, scr, n_items);
+    for (int i = 0; i < n_it; ++i) {
+      const uint32_t r0 = (uint32_t)(i * kBinSlice);
+      const uint32_t ln = (bin_len - r0) < (uint32_t)kBinSlice ? bin_len - r0 : (uint32_t)kBinSlice;
+      desc[it0 + i] = make_uint2((uint32_t)tid * (uint32_t)a.bin_cap + r0, ln);
+    }
+    __shared__ int s_nb;
+    if (tid == 0) s_nb = 0;
+    __syncthreads();
+    const size_t area = (size_t)a.bin_P * a.bin_cap;
+    constexpr size_t rbytes = W8 ? 8 : 4;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)a.bins + (size_t)b * area * rbytes), 0,
+        (int)(area * rbytes), kBufWord3);
+    for (;;) {
+      int g0 = 0;
+      if (lane == 0)
+        g0 = __hip_atomic_fetch_add(&s_nb, GB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      g0 = __builtin_amdgcn_readfirstlane(g0);
+      if (g0 >= n_items) break;
+      uint2 d[GB];
+      uint32_t r[GB][RB], x[GB][W8 ? RB : 1];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        d[u] = desc[g0 + u];  // past n_items: stale or padding, masked
+        if (g0 + u >= n_items) d[u].y = 0u;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          const uint32_t idx = (uint32_t)(k * 64 + lane);
+          const uint32_t e = idx < d[u].y ? d[u].x + idx : kOobIndex;
+          if constexpr (W8) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(e * 8u), 0, 0);
+            r[u][k] = v[0];
+            x[u][k] = v[1];
+          } else {
+            r[u][k] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(e * 4u), 0, 0);
+          }
+        }
+      }
+      // ALU work while the loads are in flight
+      if (rounds_done < n_rounds) drive_round(rounds_done++);
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          const uint32_t idx = (uint32_t)(k * 64 + lane);
+          if (idx < d[u].y) {
+            const uint32_t rr = r[u][k];
+            const uint32_t sel = 0u - ((rr >> 15) & 1u);  // all ones: inhibitory
+            const float m0 = __uint_as_float((__float_as_uint(a.wm0_e) & ~sel) |
+                                             (__float_as_uint(a.wm0_i) & sel));
+            const float m1 = __uint_as_float((__float_as_uint(a.wm1_e) & ~sel) |
+                                             (__float_as_uint(a.wm1_i) & sel));
+            float w;
+            if constexpr (W8) w = __uint_as_float(x[u][k]);
+            else w = __uint_as_float(rr & 0xffff0000u);
+            const int v = (int)fmaf(m1, w, m0);  // conversion truncates toward zero
+            __hip_atomic_fetch_add((unsigned long long*)&win[rr & ((1u << kBinSlotBits) - 1u)],
+                                   (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+    }
+    // events that found their region full: fixed-point spill rows
+    if (spill_on) {
+      for (int i = tid; i < a.Dmax * nb; i += kSliceThreads) {
+        const int q = i / nb, n = i - q * nb;
+        long long* cell = a.spill + (int64_t)q * a.N + j0 + n;
+        const long long v = *cell;
+        if (v != 0) {
+          __hip_atomic_fetch_add((unsigned long long*)&win[q * B + n], (unsigned long long)v,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          *cell = 0;
+        }
+      }
+      if (tid == 0) a.spill_flag[b] = 0;
+    }
+  } else if (!BIN && a.do_deliver) {
     // overflow beyond the list's capacity is flagged by its writer
     const int64_t total = total_raw < a.in_cap ? total_raw : a.in_cap;
     __syncthreads();  // thr / zeroing visible
@@ -771,8 +1055,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         int rr = r0 + q;
         while (rr >= a.L) rr -= a.L;
         const int64_t at = (int64_t)rr * a.N + j0 + n;
-        if constexpr (FX) carry[q * B + n] = from_fixed(a.rbq[at], a.fx_inv);
-        else carry[q * B + n] = a.rb[at];
+        carry[q * B + n] = a.rb[at];
       }
     }
     // rows at or past rb_hi hold no earlier input
@@ -967,13 +1250,13 @@ struct SingleArgs {
   SliceArgs a;
   int32_t per_xcd;
 };
-template <int WF, bool FX>
+template <int WF, bool BIN>
 __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
   const SingleArgs* p = (const SingleArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   const int gx = blockIdx.x;
   const int b = (gx & 7) * p->per_xcd + (gx >> 3);
   if (b >= p->a.NB) return;
-  slice_block<WF, FX>(p->a, b);
+  slice_block<WF, BIN>(p->a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,14 +1268,6 @@ __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64
   if (i >= rows * N) return;
   const int64_t t = t_lo + i / N;
   rb[(t % L) * N + (i % N)] = 0.f;
-}
-
-__global__ void k_zero_rows64(long long* rb, int64_t N, int32_t L, int64_t t_lo, int64_t t_hi) {
-  const int64_t rows = t_hi - t_lo;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows * N) return;
-  const int64_t t = t_lo + i / N;
-  rb[(t % L) * N + (i % N)] = 0;
 }
 
 __device__ __forceinline__ uint32_t half32(const uint64_t w[4], int64_t t) {
@@ -1095,17 +1370,9 @@ hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_deliver_sm(hipStream_t s, const SmDeliverArgs& a) {
-  hipLaunchKernelGGL(k_deliver_sm, dim3(2048), dim3(kSmThreads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_rows64(hipStream_t s, long long* rb, int64_t N, int32_t L, int64_t t_lo,
-                              int64_t t_hi) {
-  if (t_hi <= t_lo) return hipSuccess;
-  const int64_t n = (t_hi - t_lo) * N;
-  hipLaunchKernelGGL(k_zero_rows64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rb, N, L,
-                     t_lo, t_hi);
+hipError_t launch_bin(hipStream_t s, const BinArgs& a, int32_t P, size_t lds, bool w8) {
+  if (w8) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)P), dim3(kBinThreads), lds, s, a);
+  else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)P), dim3(kBinThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1147,11 +1414,10 @@ hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wfor
   sa.a = a;
   sa.per_xcd = (a.NB + 7) / 8;
   const dim3 grid((unsigned)(8 * sa.per_xcd)), block(kSliceThreads);
-  if (a.rbq) {
-    // fixed-point ring: update only (the source-major delivery is its own
-    // kernel), so the record form does not matter
-    if (a.do_deliver) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_slice1<WF_FP32, true>), grid, block, lds, s, sa);
+  if (a.bins) {
+    // binned records: 8 bytes (FP32 weight) or 4 (BF16 bits)
+    if (wform == WF_FP32) hipLaunchKernelGGL((k_slice1<WF_FP32, true>), grid, block, lds, s, sa);
+    else hipLaunchKernelGGL((k_slice1<WF_BF16, true>), grid, block, lds, s, sa);
     return hipGetLastError();
   }
   switch (wform) {

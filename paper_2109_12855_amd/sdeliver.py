@@ -51,6 +51,7 @@ class sd_config(C.Structure):
         ("record_spikes", C.c_int32),
         ("record_cap", C.c_int64),
         ("layout", C.c_int32),
+        ("bin_cap", C.c_int32),
     ]
 
 

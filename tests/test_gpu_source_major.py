@@ -1,12 +1,12 @@
 """The source-major layout on the GPU: tables, delivery and dynamics against
-the oracle, identity with the block-major layout, and the one-GPU share of
-the brain-scale network (1.27e10 synapses) on a target sample.
+the oracle, identity with the block-major layout, the spill path of the
+binning pass, and the one-GPU share of the brain-scale network (1.27e10
+synapses) on a target sample.
 
-Both layouts add every weight into a 64-bit fixed-point window with the same
-quantum (exact integer sums), so one delivery gives identical rings in either
-layout; over a run the block-major layout rounds a step's input per
-delivering slice and the source-major one rounds the total once, so runs are
-identical where every step's input comes from one delivery.
+Both layouts add every weight of a delivery into a 64-bit fixed-point LDS
+window with the same quantum (exact integer sums, in any order) and round
+each window cell to FP32 once, so rings, spikes and state are identical
+between the layouts, and between binning regions of any size.
 """
 import numpy as np
 import pytest
@@ -64,23 +64,63 @@ def test_closed_loop_tiny(case):
     assert t_bad is None or explained, (t_bad, info)
 
 
-def test_layouts_identical_dynamics():
-    """Delta net with one delay (every step's input comes from one delivery):
-    block-major and source-major runs are identical in spikes and state."""
-    res = []
-    for layout in (sdeliver.SD_LAYOUT_BLOCK, SM):
-        net = sdeliver.Net(dict(W.DELTA_SMALL, record_spikes=1, layout=layout)).build()
-        net.simulate_steps(1000)
-        st, idx = net.spikes()
-        res.append((st, idx, net.state(), net.stats()))
-        net.close()
-    (sa, ia, xa, ta), (sb, ib, xb, tb) = res
+def _run(cfg, steps):
+    net = sdeliver.Net(dict(cfg, record_spikes=1)).build()
+    net.simulate_steps(steps)
+    st, idx = net.spikes()
+    out = (st, idx, net.state(), net.stats())
+    net.close()
+    return out
+
+
+def _same_run(ra, rb):
+    (sa, ia, xa, ta), (sb, ib, xb, tb) = ra, rb
     assert len(sa) > 0
     assert np.array_equal(sa, sb) and np.array_equal(ia, ib)
-    for k in ("V", "r"):
-        assert np.array_equal(xa[k], xb[k]), k
+    for k in ("V", "y1", "y2", "r"):
+        if k in xa:
+            assert np.array_equal(xa[k], xb[k]), k
     for k in ("events_delivered", "spikes_delivered", "spikes_emitted"):
         assert ta[k] == tb[k], k
+
+
+@pytest.mark.parametrize("cfg,steps", [
+    (W.DELTA_SMALL, 1000),
+    (W.tiny(model=1, n=2111, k=300, seed=8, d_lo=10, d_hi=20), 600),
+])
+def test_layouts_identical_dynamics(cfg, steps):
+    """Block-major and source-major runs are identical in spikes and state
+    (one delay, and delays spread over 10-20 steps)."""
+    _same_run(_run(dict(cfg, layout=sdeliver.SD_LAYOUT_BLOCK), steps),
+              _run(dict(cfg, layout=SM), steps))
+
+
+@pytest.mark.parametrize("wform", [0, 2])
+def test_spill_path_identical(wform):
+    """Regions of 4 records: nearly every event of a delivery takes the
+    fixed-point spill path, and the ring equals the one from ample regions
+    and the block-major layout's, cell by cell."""
+    cfg = dict(W.tiny(model=1, n=2111, k=300, seed=8, d_lo=10, d_hi=20), wform=wform)
+    n = cfg["n_exc"] + cfg["n_inh"]
+    src, lag = W.replay_spikes(n, 700, cfg["d_min"], seed=5)
+    rings, evs = [], []
+    for over in (dict(layout=SM, bin_cap=4), dict(layout=SM), dict(layout=sdeliver.SD_LAYOUT_BLOCK)):
+        for count in (False, True):
+            net = sdeliver.Net(dict(cfg, **over)).build()
+            net.set_count_mode(count)
+            net.deliver(*_dev(src, lag), 0)
+            rings.append(net.ring())
+            evs.append(net.stats()["events_delivered"])
+            net.close()
+    for i in (2, 4):
+        assert np.array_equal(rings[0], rings[i]) and np.array_equal(rings[1], rings[i + 1]), i
+    assert len(set(evs)) == 1
+
+
+def test_spill_path_closed_loop():
+    """A closed-loop run with regions of 4 records equals the default run."""
+    cfg = dict(W.tiny(model=1, n=2111, k=300, seed=8, d_lo=10, d_hi=20), layout=SM)
+    _same_run(_run(dict(cfg, bin_cap=4), 300), _run(cfg, 300))
 
 
 @pytest.mark.parametrize("cfg,n_spikes", [
@@ -91,8 +131,7 @@ def test_layouts_identical_dynamics():
 def test_layouts_identical_rings(cfg, n_spikes):
     """One delivery (weights and counts) into a fresh ring: both layouts
     hold the same exact fixed-point sums, rounded once, so every cell is
-    identical.  (Over a run, a step receiving from two slices is rounded
-    per part in the block-major layout and once in the source-major one.)"""
+    identical."""
     n = cfg["n_exc"] + cfg["n_inh"]
     src, lag = W.replay_spikes(n, n_spikes, cfg["d_min"], seed=n_spikes)
     rings = {}
