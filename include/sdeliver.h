@@ -112,10 +112,10 @@ typedef struct {
   int32_t record_spikes;     /* keep a device raster of emitted spikes (0/1)    */
   int64_t record_cap;        /* raster capacity in spikes (0 = automatic)       */
   int32_t layout;            /* sd_layout                                       */
-  int32_t bin_cap;           /* source-major: records per (target block,
-                                binning workgroup) region and slice, at most
-                                1024; events past it take a slower exact path
-                                (0 = from the expected rate)                   */
+  int32_t bin_cap;           /* source-major: binned records per (target
+                                block, binning workgroup) region and delivery,
+                                at most 1024; events past it take a slower
+                                exact path (0 = from the expected rate)        */
 } sd_config;
 
 typedef struct {

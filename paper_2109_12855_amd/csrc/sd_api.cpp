@@ -383,7 +383,7 @@ int32_t auto_bin_cap(const sd_config& c, const Layout& L) {
   const double e = spikes / kBinProducers * per_src / std::max<int32_t>(L.NB, 1);
   double cap = 1.25 * e + 6.0 * std::sqrt(e) + 64.0;
   int64_t k = ((int64_t)std::ceil(cap) + 63) / 64 * 64;
-  return (int32_t)std::min<int64_t>(1024, std::max<int64_t>(64, k));
+  return (int32_t)std::min<int64_t>(kBinMaxCap, std::max<int64_t>(64, k));
 }
 
 // Block-major geometry and its limits (LDS window, u16/packed offsets,
@@ -468,13 +468,17 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     L->NB = (int32_t)((L->N + L->B - 1) / L->B);
     L->bin_P = kBinProducers;
     L->bin_cap = c->bin_cap > 0 ? c->bin_cap : auto_bin_cap(*c, *L);
-    if (L->bin_cap > 1024) {
+    if (L->bin_cap > kBinMaxCap) {
       *why = "bin_cap must be at most 1024";
       return SD_EINVAL;
     }
+    if ((int64_t)L->NB * L->bin_P * L->bin_cap >= (1LL << 31)) {
+      *why = "binned records of all target blocks exceed 2^31; lower bin_cap";
+      return SD_EUNSUPPORTED;
+    }
     const bool w8 = c->wform == SD_W_FP32;
     L->bin_U = 0;
-    for (int u = w8 ? 16 : kBinMaxU; u >= 4; u -= 4)
+    for (int u = w8 ? kBinMaxU8 : kBinMaxU; u >= 4; u -= 4)
       if (bin_lds_bytes(L->NB, u, w8) + 64 <= kLdsBudget) {
         L->bin_U = u;
         break;
@@ -569,8 +573,8 @@ SliceArgs base_args(sd_ctx* c) {
   if (c->sm) {
     a.bins = c->bins;
     a.bin_cnt = c->bin_cnt;
-    a.bin_P = c->bin_P;
     a.bin_cap = c->bin_cap;
+    a.bin_P = c->bin_P;
     a.spill = c->spill;
     a.spill_flag = c->spill_flag;
   }

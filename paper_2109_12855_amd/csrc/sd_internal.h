@@ -137,7 +137,7 @@ struct BinArgs {
   int64_t src_e_end;
   float wm0_e, wm1_e, wm0_i, wm1_i;  // fixed-point weights of spilled events
   void* bins;                     // [NB][P][cap] records
-  uint32_t* bin_cnt;              // [NB][P]
+  uint32_t* bin_cnt;              // [NB][P] records per region
   long long* spill;               // [Dmax][N]
   int32_t* spill_flag;            // [NB]
   unsigned long long* ev_count;
@@ -151,8 +151,10 @@ struct BinArgs {
 constexpr int kBinSlotBits = 15;
 constexpr int kBinThreads = 1024;
 constexpr int kBinSpikes = 512;   // spikes resolved per descriptor batch
-constexpr int kBinMaxU = 20;      // events per thread per sorting chunk (4-byte records)
+constexpr int kBinMaxU = 16;      // events per thread per sorting chunk (4-byte records)
+constexpr int kBinMaxU8 = 12;     // the same for 8-byte records
 constexpr int kBinProducers = 256;
+constexpr int kBinMaxCap = 1024;  // records per region (consumer work items <= 1024)
 constexpr int kBinSlice = 256;    // records per consumer work item
 size_t bin_lds_bytes(int NB, int U, bool w8);
 constexpr int kTgtBits = 26;

@@ -367,13 +367,14 @@ __global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
 // atomics are involved.  A region that fills up sends further events to the
 // fixed-point spill rows with global atomics and flags the block.
 struct BinLds {
-  size_t stage, cnt, cur, pre, lo, mt, scr, total;
+  size_t stage, dst, cnt, cur, pre, lo, mt, scr, total;
 };
 __host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   BinLds L;
   size_t o = 0;
   L.stage = o; o = up(o + (size_t)U * kBinThreads * (w8 ? 8 : 4));  // sorted chunk
+  L.dst = o;   o = up(o + (size_t)U * kBinThreads * 4);  // destination of each sorted record
   L.cnt = o;   o = up(o + (size_t)(NB + 1) * 4);  // counts, then bin starts
   L.cur = o;   o = up(o + (size_t)NB * 4);        // records in each region so far
   L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per spike
@@ -392,13 +393,13 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   // segment (the whole struct in scalar registers would spill)
   const BinArgs& a = *(const BinArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int nwv = kBinThreads / 64;
+  const int tid = threadIdx.x;
   const int p = blockIdx.x, P = gridDim.x;
   const int NB = a.NB, B = a.B, U = a.U, cap = a.cap;
   const BinLds Lo = bin_lds_layout(NB, U, W8);
   uint32_t* stage = (uint32_t*)(lds_raw + Lo.stage);
   uint2* stage2 = (uint2*)(lds_raw + Lo.stage);
+  uint32_t* dst = (uint32_t*)(lds_raw + Lo.dst);
   uint32_t* cnt = (uint32_t*)(lds_raw + Lo.cnt);
   uint32_t* cur = (uint32_t*)(lds_raw + Lo.cur);
   unsigned long long* pre = (unsigned long long*)(lds_raw + Lo.pre);
@@ -415,8 +416,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   for (int i = tid; i < NB; i += kBinThreads) cur[i] = 0u;
   unsigned long long ev = 0;
   const uint32_t tmask = (1u << kTgtBits) - 1u;
-  const size_t region0 = (size_t)p * cap;  // this workgroup's region in a block's area
-  const size_t area = (size_t)P * cap;     // records per block
+  const uint32_t region0 = (uint32_t)p * (uint32_t)cap;  // this workgroup's region in a block's area
+  const uint32_t area = (uint32_t)P * (uint32_t)cap;     // records per block
 
   for (int64_t sb = s_lo; sb < s_hi; sb += kBinSpikes) {
     const int ns = (int)((s_hi - sb) < kBinSpikes ? (s_hi - sb) : kBinSpikes);
@@ -445,9 +446,16 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
 
     // (2) chunks of U * 1024 events of the batch, event f of the batch at
     // thread f % 1024, slot f / 1024 (consecutive lanes read consecutive
-    // records of a segment)
+    // records of a segment).  Each thread's events of a chunk sit in
+    // registers: target|delay word, weight bits, and lag / population packed
+    // four to a register.  A chunk's loads are issued while the previous
+    // chunk is written out.
     const unsigned long long E_c = (unsigned long long)U * kBinThreads;
-    for (unsigned long long f0 = 0; f0 < n_batch; f0 += E_c) {
+    constexpr int UM = W8 ? kBinMaxU8 : kBinMaxU;  // register budget
+    uint32_t tdk[UM], wbr[UM], rec8[W8 ? UM : 1], m4[UM / 4];
+    auto issue = [&](unsigned long long f0) {
+      const unsigned long long left = n_batch - f0;
+      const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
       // spike of this thread's first event: the last one starting at or
       // before it (pre[ns] = n_batch lies past every event)
       int sp = 0;
@@ -461,53 +469,52 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
         }
         sp = l;
       }
-      constexpr int UM = W8 ? 16 : kBinMaxU;  // register budget
+#pragma unroll
+      for (int u = 0; u < UM / 4; ++u) m4[u] = 0u;
+#pragma unroll
+      for (int u = 0; u < UM; ++u) {
+        const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+        tdk[u] = 0u;
+        wbr[u] = 0u;
+        if (u < U && fr < n_ev) {
+          const unsigned long long f = f0 + fr;
+          while (pre[sp + 1] <= f) ++sp;
+          const unsigned long long e = lo[sp] + (f - pre[sp]);
+          tdk[u] = a.tgtd[e];
+          if constexpr (W8) wbr[u] = ((const uint32_t*)a.wbits)[e];
+          else wbr[u] = ((const uint16_t*)a.wbits)[e];
+          const uint32_t m = mt[sp];
+          m4[u >> 2] |= ((m & 31u) | ((m >> 10) & 32u)) << ((u & 3) * 8);  // lag | inh << 5
+        }
+      }
+    };
+    if (n_batch > 0) issue(0);
+    for (unsigned long long f0 = 0; f0 < n_batch; f0 += E_c) {
       const unsigned long long left = n_batch - f0;
       const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
-      uint32_t key[UM], rec[UM], wrd[W8 ? UM : 1];
+      // classify: tdk[u] becomes the event's key (block << 16 | rank in the
+      // block's bin), wbr[u] (4-byte form) or rec8[u] (FP32) its record
 #pragma unroll
-      for (int u = 0; u < UM; ++u) key[u] = 0xffffffffu;  // no event
-#pragma unroll
-      for (int u0 = 0; u0 < UM; u0 += 4) {
-        if (u0 < U) {
-          uint32_t td[4], wb[4], m8[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const uint32_t fr = (uint32_t)((u0 + k) * kBinThreads + tid);
-            td[k] = 0u;
-            wb[k] = 0u;
-            m8[k] = 0u;
-            if (fr < n_ev) {
-              const unsigned long long f = f0 + fr;
-              while (pre[sp + 1] <= f) ++sp;
-              const unsigned long long e = lo[sp] + (f - pre[sp]);
-              td[k] = a.tgtd[e];
-              if constexpr (W8) wb[k] = ((const uint32_t*)a.wbits)[e];
-              else wb[k] = ((const uint16_t*)a.wbits)[e];
-              m8[k] = mt[sp];
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int u = u0 + k;
-            const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
-            rec[u] = 0u;
-            if constexpr (W8) wrd[u] = wb[k];
-            if (fr < n_ev) {
-              const int tgt = (int)(td[k] & tmask);
-              // block = tgt / B from an FP32 estimate, corrected by one step
-              int blk = (int)((float)tgt * a.inv_B);
-              int off = tgt - blk * B;
-              if (off < 0) { --blk; off += B; }
-              if (off >= B) { ++blk; off -= B; }
-              const int q = (int)(m8[k] & 31u) + (int)(td[k] >> kTgtBits);
-              rec[u] = (uint32_t)(q * B + off) | (m8[k] & 0x8000u);
-              if constexpr (!W8) rec[u] |= wb[k] << 16;
-              const uint32_t rank = __hip_atomic_fetch_add(&cnt[blk], 1u, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-              key[u] = ((uint32_t)blk << 16) | rank;
-            }
-          }
+      for (int u = 0; u < UM; ++u) {
+        const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+        const uint32_t td = tdk[u];
+        tdk[u] = 0xffffffffu;  // no event
+        if constexpr (W8) rec8[u] = 0u;
+        if (u < U && fr < n_ev) {
+          const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 63u;
+          const int tgt = (int)(td & tmask);
+          // block = tgt / B from an FP32 estimate, corrected by one step
+          int blk = (int)((float)tgt * a.inv_B);
+          int off = tgt - blk * B;
+          if (off < 0) { --blk; off += B; }
+          if (off >= B) { ++blk; off -= B; }
+          const int q = (int)(m & 31u) + (int)(td >> kTgtBits);
+          const uint32_t r = (uint32_t)(q * B + off) | ((m & 32u) << 10);
+          if constexpr (W8) rec8[u] = r;
+          else wbr[u] = r | (wbr[u] << 16);
+          const uint32_t rank = __hip_atomic_fetch_add(&cnt[blk], 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+          tdk[u] = ((uint32_t)blk << 16) | rank;
         }
       }
       __syncthreads();
@@ -527,67 +534,61 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
         if (tid == 0) cnt[NB] = n_chunk;
       }
       __syncthreads();
-      // (4) scatter into bin order
+      // (4) scatter into bin order, with each record's destination: its
+      // index in the bin area (block * P * cap + this region's start +
+      // fill + rank), or kNoDst | block when the region is full
+      constexpr uint32_t kNoDst = 0x80000000u;
 #pragma unroll
       for (int u = 0; u < UM; ++u) {
-        if (key[u] != 0xffffffffu) {
-          const uint32_t at = cnt[key[u] >> 16] + (key[u] & 0xffffu);
-          if constexpr (W8) stage2[at] = make_uint2(rec[u], wrd[u]);
-          else stage[at] = rec[u];
+        if (tdk[u] != 0xffffffffu) {
+          const uint32_t blk = tdk[u] >> 16;
+          const uint32_t at = cnt[blk] + (tdk[u] & 0xffffu);
+          const uint32_t pos = cur[blk] + (tdk[u] & 0xffffu);
+          if constexpr (W8) stage2[at] = make_uint2(rec8[u], wbr[u]);
+          else stage[at] = wbr[u];
+          dst[at] = pos < (uint32_t)cap ? blk * area + region0 + pos : kNoDst | blk;
         }
       }
       __syncthreads();
-      // (5) append each bin's run to this workgroup's region of the block:
-      // a wave takes 64 blocks, lane l holding block g0 + l's start, count
-      // and fill; quarters of the wave then copy four blocks' runs at a time
-      // (runs of ~E_c / NB records: coalesced stores of that length)
-      for (int g0 = wv * 64; g0 < NB; g0 += nwv * 64) {
-        const int bl = g0 + lane;
-        uint32_t st = 0, n = 0, base = 0;
-        if (bl < NB) {
-          st = cnt[bl];
-          n = cnt[bl + 1] - st;
-          base = cur[bl];
-        }
-        const int sub = lane >> 4, sl = lane & 15;
-        for (int j = 0; j < 64; j += 4) {
-          const int lj = j + sub;
-          const uint32_t st_j = (uint32_t)__shfl((int)st, lj, 64);
-          const uint32_t n_j = (uint32_t)__shfl((int)n, lj, 64);
-          const uint32_t base_j = (uint32_t)__shfl((int)base, lj, 64);
-          const int b = g0 + lj;
-          for (uint32_t k = (uint32_t)sl; k < n_j; k += 16) {
-            const uint32_t pos = base_j + k;
-            if ((int)pos < cap) {
-              const size_t at = (size_t)b * area + region0 + pos;
-              if constexpr (W8) ((uint2*)a.bins)[at] = stage2[st_j + k];
-              else ((uint32_t*)a.bins)[at] = stage[st_j + k];
-            } else {
-              // region full: add the event's fixed-point weight into the
-              // spill rows with a global atomic
-              uint32_t r;
-              float w;
-              if constexpr (W8) {
-                const uint2 x = stage2[st_j + k];
-                r = x.x;
-                w = __uint_as_float(x.y);
-              } else {
-                r = stage[st_j + k];
-                w = __uint_as_float(r & 0xffff0000u);
-              }
-              const int slot = (int)(r & ((1u << kBinSlotBits) - 1u));
-              const int q = slot / B, off = slot - q * B;
-              const bool inh = (r & 0x8000u) != 0u;
-              const long long v =
-                  (long long)(int)fmaf(inh ? a.wm1_i : a.wm1_e, w, inh ? a.wm0_i : a.wm0_e);
-              atomicAdd((unsigned long long*)&a.spill[(int64_t)q * a.N + (int64_t)b * B + off],
-                        (unsigned long long)v);
-              a.spill_flag[b] = 1;
-            }
+      // the next chunk's loads (the registers are free after the scatter)
+      if (f0 + E_c < n_batch) issue(f0 + E_c);
+      // (5) every thread stores sorted records f, f + 1024, ...: a bin's run
+      // goes to consecutive addresses (coalesced stores of ~E_c / NB
+      // records), then the fills advance
+      const uint32_t n_chunk = cnt[NB];
+#pragma unroll
+      for (int u = 0; u < UM; ++u) {
+        const uint32_t i = (uint32_t)(u * kBinThreads + tid);
+        if (i < n_chunk) {
+          const uint32_t d = dst[i];
+          uint32_t r, wx = 0u;
+          if constexpr (W8) {
+            const uint2 x = stage2[i];
+            r = x.x;
+            wx = x.y;
+          } else {
+            r = stage[i];
+          }
+          if (!(d & kNoDst)) {
+            if constexpr (W8) ((uint2*)a.bins)[d] = make_uint2(r, wx);
+            else ((uint32_t*)a.bins)[d] = r;
+          } else {
+            // region full: add the event's fixed-point weight into the
+            // spill rows with a global atomic
+            const int bk = (int)(d & ~kNoDst);
+            const float w = W8 ? __uint_as_float(wx) : __uint_as_float(r & 0xffff0000u);
+            const int slot = (int)(r & ((1u << kBinSlotBits) - 1u));
+            const int q = slot / B, off = slot - q * B;
+            const bool inh = (r & 0x8000u) != 0u;
+            const long long v =
+                (long long)(int)fmaf(inh ? a.wm1_i : a.wm1_e, w, inh ? a.wm0_i : a.wm0_e);
+            atomicAdd((unsigned long long*)&a.spill[(int64_t)q * a.N + (int64_t)bk * B + off],
+                      (unsigned long long)v);
+            a.spill_flag[bk] = 1;
           }
         }
-        if (bl < NB) cur[bl] = base + n;
       }
+      for (int b = tid; b < NB; b += kBinThreads) cur[b] += cnt[b + 1] - cnt[b];
       __syncthreads();
       for (int i = tid; i <= NB; i += kBinThreads) cnt[i] = 0u;
       __syncthreads();
@@ -830,7 +831,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     // range).  The record holds the window slot, so the adds need no
     // per-item state.
     constexpr bool W8 = WF == WF_FP32;
-    constexpr int GB = 4, RB = kBinSlice / 64;
+    constexpr int GB = 8, RB = kBinSlice / 64;
     int n_items;
     const int n_it = (int)((bin_len + kBinSlice - 1) / kBinSlice);
     const int it0 = block_excl_scan<int>(n_it, scr, n_items);
