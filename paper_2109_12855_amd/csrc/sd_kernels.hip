@@ -1068,6 +1068,45 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   __syncthreads();
   if (tid == 0 && a.do_deliver && s_ev) atomicAdd(a.ev_count, s_ev);
 
+  // ---- rows of the window due in later slices go to the HBM ring -------
+  // Rows [t_first, w_lo + Dmax): all window reads first, then the stores
+  // (adds into rows that already hold earlier deliveries).  Threads without
+  // a neuron to update write them while the others update; when every
+  // thread updates, all write them afterwards.
+  auto flush_rows = [&](int t0, int stride) {
+    constexpr int kFl = 8;
+    const double inv = a.fx_inv;
+    int64_t t_first = a.t_upd + a.n_upd;
+    if (t_first < w_lo) t_first = w_lo;
+    const int nrows = (int)(w_lo + a.Dmax - t_first);
+    const int q0 = (int)(t_first - w_lo);
+    const int row0 = (int)(t_first % a.L);
+    int64_t add_rows = a.rb_hi - t_first;  // leading rows that are added into
+    if (add_rows < 0) add_rows = 0;
+    if (add_rows > nrows) add_rows = nrows;
+    const int n_add = (int)add_rows;
+    for (int n = t0; n < nb; n += stride) {
+      for (int k0 = 0; k0 < nrows; k0 += kFl) {
+        float v[kFl];
+#pragma unroll
+        for (int k = 0; k < kFl; ++k)
+          if (k0 + k < nrows) v[k] = from_fixed(win[(q0 + k0 + k) * B + n], inv);
+#pragma unroll
+        for (int k = 0; k < kFl; ++k) {
+          if (k0 + k < nrows) {
+            int row = row0 + k0 + k;
+            if (row >= a.L) row -= a.L;  // row0 < L and nrows <= Dmax < L
+            float* p = a.rb + (int64_t)row * a.N + j0 + n;
+            if (k0 + k < n_add) *p += v[k];
+            else *p = v[k];
+          }
+        }
+      }
+    }
+  };
+  const bool split = a.n_upd > 0 && nb < kSliceThreads;
+  if (a.do_deliver && split && tid >= nb) flush_rows(tid - nb, kSliceThreads - nb);
+
   // ---- update the next slice's steps (exact propagation, Sec. 2.1) -------
   if (a.n_upd > 0) {
     const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
@@ -1143,40 +1182,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     }
   }
 
-  // ---- rows of the window due in later slices go to the HBM ring -------
-  if (a.do_deliver) {
-    // rows [t_first, w_lo + Dmax): all window reads first, then the stores
-    // (adds into rows that already hold earlier deliveries)
-    constexpr int kFl = 8;
-    const double inv = a.fx_inv;
-    int64_t t_first = a.t_upd + a.n_upd;
-    if (t_first < w_lo) t_first = w_lo;
-    const int nrows = (int)(w_lo + a.Dmax - t_first);
-    const int q0 = (int)(t_first - w_lo);
-    const int row0 = (int)(t_first % a.L);
-    int64_t add_rows = a.rb_hi - t_first;  // leading rows that are added into
-    if (add_rows < 0) add_rows = 0;
-    if (add_rows > nrows) add_rows = nrows;
-    const int n_add = (int)add_rows;
-    for (int n = tid; n < nb; n += kSliceThreads) {
-      for (int k0 = 0; k0 < nrows; k0 += kFl) {
-        float v[kFl];
-#pragma unroll
-        for (int k = 0; k < kFl; ++k)
-          if (k0 + k < nrows) v[k] = from_fixed(win[(q0 + k0 + k) * B + n], inv);
-#pragma unroll
-        for (int k = 0; k < kFl; ++k) {
-          if (k0 + k < nrows) {
-            int row = row0 + k0 + k;
-            if (row >= a.L) row -= a.L;  // row0 < L and nrows <= Dmax < L
-            float* p = a.rb + (int64_t)row * a.N + j0 + n;
-            if (k0 + k < n_add) *p += v[k];
-            else *p = v[k];
-          }
-        }
-      }
-    }
-  }
+  if (a.do_deliver && !split) flush_rows(tid, kSliceThreads);
   __syncthreads();
 
   // ---- compaction: this block's new spikes, (lag, neuron) ordered --------
