@@ -277,6 +277,35 @@ sd_status sd_batch_build(sd_batch* b);
 /* advance every member by n_steps (or round(t_ms / h) steps) */
 sd_status sd_batch_simulate_steps(sd_batch* b, int64_t n_steps);
 sd_status sd_batch_simulate(sd_batch* b, double t_ms);
+/* on != 0: steady-state stretches of at least 12 slices run as replays of a
+ * captured HIP graph of 6 batched slices (the slice cycle of Sec. 2.1
+ * repeats with the same launches; the spike lists alternate between two
+ * buffers and their counters rotate over three, so the arguments of a
+ * period equal the previous period's moved on by 6 * d_min steps, which a
+ * small kernel at the end of the graph applies on the device).  Results
+ * are identical to eager launches.  The graph is captured at first use on
+ * a private stream and replayed on the batch's stream. */
+sd_status sd_batch_set_graph(sd_batch* b, int32_t on);
+/* graph replays issued so far (each runs 6 slices), -1 for NULL */
+int64_t sd_batch_graph_launches(const sd_batch* b);
+
+/* --- block-size autotuning -------------------------------------------------
+ * Block sizes for n networks (n = 1: one context; n > 1: a batch, whose
+ * members must be block-major).  For each target T in targets[0..n_targets)
+ * member i gets block_neurons = ceil(N_i / T) rounded up to 64, lowered in
+ * steps of 64 until its layout fits; each candidate is created, built and
+ * timed over `slices` slices after `warmup` slices on a private stream of
+ * the current device, and the fastest candidate's sizes go to
+ * h_block_neurons[0..n), its time per slice (us) to *us_per_slice (may be
+ * NULL).  cache_path (may be NULL) names a JSON file of earlier results
+ * keyed by device architecture and a hash of the configurations and tuning
+ * options: a hit returns the stored sizes without timing, a miss adds the
+ * result.  The configurations' own block_neurons are ignored.  Needs the
+ * device memory of one candidate at a time.  SD_EUNSUPPORTED: no candidate
+ * ran; SD_EINVAL: bad arguments, or the cache file could not be written. */
+sd_status sd_autotune(const sd_config* cfgs, int32_t n, const int32_t* targets,
+                      int32_t n_targets, int32_t warmup, int32_t slices,
+                      const char* cache_path, int32_t* h_block_neurons, double* us_per_slice);
 
 #ifdef __cplusplus
 }

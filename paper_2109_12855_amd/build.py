@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdeliver.so")
-SOURCES = [os.path.join(CSRC, "sd_api.cpp"), os.path.join(CSRC, "sd_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "sd_api.cpp"), os.path.join(CSRC, "sd_autotune.cpp"),
+           os.path.join(CSRC, "sd_kernels.hip")]
 ARCH = os.environ.get("SD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

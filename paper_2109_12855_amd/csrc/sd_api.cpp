@@ -293,11 +293,27 @@ struct sd_ctx {
 
 // Independent networks advanced together: every slice of all members is
 // one fused launch over the union of their target blocks.
+// Captured batch slices: in the steady state (every member has a pending
+// delivery, t_now on a slice boundary, and its ring valid up to t_now -
+// d_min + d_max), slice k + kGraphSlices launches with the arguments of
+// slice k moved on by kGraphSlices * d_min steps: the spike lists alternate
+// between two buffers and the list counters rotate over three words.
+constexpr int kGraphSlices = 6;
+
 struct sd_batch {
   std::vector<sd_ctx*> nets;
   hipStream_t stream = nullptr;
   std::string err;
   SliceLauncher lau;
+  // graph of kGraphSlices batched launches + the argument shift, replayed
+  bool graph_on = false;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;        // capture stream (private)
+  sd::SliceArgs* g_args = nullptr;         // [kGraphSlices][n] (device)
+  sd::SliceArgs* g_host = nullptr;         // pinned staging of g_args
+  hipEvent_t g_ev = nullptr;               // staging copy done
+  bool g_pend = false;
+  int64_t g_launches = 0;                  // graph replays so far
 };
 
 namespace {
@@ -1742,8 +1758,21 @@ void sd_batch_destroy(sd_batch* bt) {
   if (bt->stream || !bt->nets.empty()) (void)hipStreamSynchronize(bt->stream);
   for (sd_ctx* c : bt->nets) sd_destroy(c);
   launcher_free(bt->lau);
+  if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+  if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+  if (bt->g_args) (void)hipFree(bt->g_args);
+  if (bt->g_host) (void)hipHostFree(bt->g_host);
+  if (bt->g_ev) (void)hipEventDestroy(bt->g_ev);
   delete bt;
 }
+
+sd_status sd_batch_set_graph(sd_batch* bt, int32_t on) {
+  if (!bt) return SD_EINVAL;
+  bt->graph_on = on != 0;
+  return SD_OK;
+}
+
+int64_t sd_batch_graph_launches(const sd_batch* bt) { return bt ? bt->g_launches : -1; }
 
 const char* sd_batch_last_error(const sd_batch* bt) { return bt ? bt->err.c_str() : "null batch"; }
 
@@ -1763,6 +1792,87 @@ sd_status sd_batch_build(sd_batch* bt) {
   }
   return SD_OK;
 }
+
+namespace {
+// Capture, once: kGraphSlices batched launches reading their arguments from
+// g_args, then the shift of those arguments to the next period.
+sd_status batch_graph(sd_batch* bt) {
+  if (bt->gexec) return SD_OK;
+  const size_t n = bt->nets.size();
+  const size_t bytes = (size_t)kGraphSlices * n * sizeof(sd::SliceArgs);
+  hipError_t e = hipMalloc((void**)&bt->g_args, bytes);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&bt->g_host, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->g_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bfail(bt, SD_EHIP, std::string("graph set-up: ") + hipGetErrorString(e));
+  const int64_t shift = (int64_t)kGraphSlices * bt->nets[0]->cfg.d_min;
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal);
+  for (int j = 0; j < kGraphSlices && e == hipSuccess; ++j)
+    e = sd::launch_slice(bt->cap_stream, bt->g_args + (size_t)j * n, bt->lau.d_map,
+                         bt->lau.n_blocks, bt->lau.lds, bt->lau.wform);
+  if (e == hipSuccess)
+    e = sd::launch_shift_args(bt->cap_stream, bt->g_args, (int32_t)(kGraphSlices * n), shift);
+  const hipError_t e2 = hipStreamEndCapture(bt->cap_stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    bt->gexec = nullptr;
+    return bfail(bt, SD_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  return SD_OK;
+}
+
+bool batch_steady(const sd_batch* bt) {
+  for (const sd_ctx* c : bt->nets) {
+    const sd_config& g = c->cfg;
+    if (!c->pend_open || c->t_now % g.d_min != 0 || c->pend_t0 != c->t_now - g.d_min ||
+        c->rb_hi != c->t_now - g.d_min + g.d_max)
+      return false;
+  }
+  return true;
+}
+
+// Run reps * kGraphSlices steady-state slices through the captured graph.
+sd_status batch_replay(sd_batch* bt, int64_t reps) {
+  sd_status st = batch_graph(bt);
+  if (st != SD_OK) return st;
+  const size_t n = bt->nets.size();
+  if (bt->g_pend) {
+    const hipError_t e = hipEventSynchronize(bt->g_ev);  // staging free again
+    if (e != hipSuccess) return bfail(bt, SD_EHIP, hipGetErrorString(e));
+    bt->g_pend = false;
+  }
+  // arguments of the next period (advances every member by kGraphSlices)
+  for (int j = 0; j < kGraphSlices; ++j)
+    for (size_t i = 0; i < n; ++i) {
+      const int32_t m = bt->nets[i]->cfg.d_min;
+      st = next_fused_slice(bt->nets[i], m, &bt->g_host[(size_t)j * n + i]);
+      if (st != SD_OK) return bfail(bt, st, sd_last_error(bt->nets[i]));
+    }
+  hipError_t e = hipMemcpyAsync(bt->g_args, bt->g_host, (size_t)kGraphSlices * n * sizeof(sd::SliceArgs),
+                                hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipEventRecord(bt->g_ev, bt->stream);
+  if (e != hipSuccess) return bfail(bt, SD_EHIP, hipGetErrorString(e));
+  bt->g_pend = true;
+  for (int64_t r = 0; r < reps; ++r) {
+    e = hipGraphLaunch(bt->gexec, bt->stream);
+    if (e != hipSuccess) return bfail(bt, SD_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    ++bt->g_launches;
+  }
+  // the host state after the further periods
+  const int64_t k = (reps - 1) * kGraphSlices;
+  for (sd_ctx* c : bt->nets) {
+    const int64_t d = k * c->cfg.d_min;
+    c->t_now += d;
+    c->pend_t0 += d;
+    c->rb_hi += d;
+    c->slices += k;
+  }
+  return SD_OK;
+}
+}  // namespace
 
 sd_status sd_batch_simulate_steps(sd_batch* bt, int64_t n_steps) {
   if (!bt || n_steps < 0) return SD_EINVAL;
@@ -1797,6 +1907,14 @@ sd_status sd_batch_simulate_steps(sd_batch* bt, int64_t n_steps) {
       }
       if (st != SD_OK) return st;
       left -= m;
+      continue;
+    }
+    const int64_t period = (int64_t)kGraphSlices * Dmin;
+    if (bt->graph_on && left >= 2 * period && batch_steady(bt)) {
+      sd_status st = flush();
+      if (st == SD_OK) st = batch_replay(bt, left / period);
+      if (st != SD_OK) return st;
+      left -= (left / period) * period;
       continue;
     }
     const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);

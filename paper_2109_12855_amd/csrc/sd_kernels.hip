@@ -1444,6 +1444,22 @@ hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wfor
   return hipGetLastError();
 }
 
+// Captured batches: the argument sets of a period of slices move on by
+// shift steps (the time fields of a steady-state fused slice).
+__global__ void k_shift_args(SliceArgs* args, int32_t n, int64_t shift) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  args[i].t_upd += shift;
+  args[i].t_slice0 += shift;
+  args[i].w_lo += shift;
+  args[i].rb_hi += shift;
+}
+
+hipError_t launch_shift_args(hipStream_t s, SliceArgs* args, int32_t n, int64_t shift) {
+  hipLaunchKernelGGL(k_shift_args, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, args, n, shift);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi) {
   if (t_hi <= t_lo) return hipSuccess;

@@ -82,7 +82,8 @@ EXPORTS = (
     "sd_export_connections", "sd_export_segments", "sd_export_block", "sd_get_tables",
     "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
     "sd_batch_size", "sd_batch_member", "sd_batch_build", "sd_batch_simulate_steps",
-    "sd_batch_simulate", "sd_save_state", "sd_load_state",
+    "sd_batch_simulate", "sd_batch_set_graph", "sd_batch_graph_launches", "sd_save_state",
+    "sd_load_state", "sd_autotune",
 )
 
 _lib = None
@@ -133,6 +134,9 @@ def lib():
         "sd_batch_build": ([vp], i32),
         "sd_batch_simulate_steps": ([vp, i64], i32),
         "sd_batch_simulate": ([vp, dbl], i32),
+        "sd_batch_set_graph": ([vp, i32], i32),
+        "sd_batch_graph_launches": ([vp], i64),
+        "sd_autotune": ([P(sd_config), i32, vp, i32, i32, i32, C.c_char_p, vp, P(dbl)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -438,6 +442,15 @@ class Batch:
     def simulate(self, t_ms: float):
         self._check(lib().sd_batch_simulate(self._h, float(t_ms)), "sd_batch_simulate")
 
+    def set_graph(self, on: bool = True):
+        """Run steady-state stretches as replays of a captured HIP graph."""
+        self._check(lib().sd_batch_set_graph(self._h, int(bool(on))), "sd_batch_set_graph")
+        return self
+
+    @property
+    def graph_launches(self) -> int:
+        return int(lib().sd_batch_graph_launches(self._h))
+
     def close(self):
         if getattr(self, "_h", None):
             for m in self.members:
@@ -450,3 +463,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune(cfgs, targets=(16, 32, 64, 128, 256), warmup: int = 10, slices: int = 20,
+             cache: str | None = None):
+    """Block sizes for one network (a single config) or a batch (several):
+    the fastest of the candidates ceil(N / T) over the targets T, timed on
+    the current device (``sd_autotune``).  Returns (block_neurons list,
+    microseconds per slice)."""
+    cfgs = [dict(c) for c in cfgs]
+    arr = (sd_config * len(cfgs))(*[make_config(c) for c in cfgs])
+    tg = np.ascontiguousarray(targets, np.int32)
+    out = np.zeros(len(cfgs), np.int32)
+    us = C.c_double()
+    rc = lib().sd_autotune(arr, len(cfgs), _ptr(tg), len(tg), int(warmup), int(slices),
+                           cache.encode() if cache else None, _ptr(out), C.byref(us))
+    if rc != SD_OK:
+        raise SdError(rc, "sd_autotune")
+    return [int(x) for x in out], float(us.value)

@@ -88,15 +88,51 @@ def test_batch_single_member():
     _check_members(bt, cfgs, [150])
 
 
+def _same_members(ga, eb, n):
+    for i in range(n):
+        sa, ia = ga.members[i].spikes()
+        sb, ib = eb.members[i].spikes()
+        assert np.array_equal(sa, sb) and np.array_equal(ia, ib), i
+        xa, xb = ga.members[i].state(), eb.members[i].state()
+        for k in ("V", "y1", "y2", "r"):
+            assert np.array_equal(xa[k], xb[k]), (i, k)
+        ta, tb = ga.members[i].stats(), eb.members[i].stats()
+        for k in ("events_delivered", "spikes_delivered", "spikes_emitted", "slices", "t_now"):
+            assert ta[k] == tb[k], (i, k)
+
+
+def test_batch_graph_equals_eager():
+    """Steady-state stretches replayed from the captured graph give the same
+    spikes, state and counters as eager launches after every call: partial
+    slices, the first delivery, replays of several periods and eager
+    remainders alternate, with host read-backs between the calls."""
+    cfgs = _small_sweep(4, seed=11)
+    ga = sdeliver.Batch(cfgs).build().set_graph(True)
+    eb = sdeliver.Batch(cfgs).build()
+    d_min = cfgs[0]["d_min"]
+    replays = []
+    for m in (7, 3, 13 * d_min, 14 * d_min - 2, 5, 4 * d_min, 27 * d_min + 3):
+        ga.simulate_steps(m)
+        eb.simulate_steps(m)
+        _same_members(ga, eb, len(cfgs))
+        replays.append(ga.graph_launches)
+    assert ga.members[0].stats()["spikes_emitted"] > 0
+    # replays happened in several calls, none in the eager batch
+    assert len(set(replays)) >= 3 and replays[-1] >= 6, replays
+    assert eb.graph_launches == 0
+
+
 def test_sweep_64_full_size():
     """The 64-network sweep at its full sizes (N up to 40,000, K up to
-    5,000), 0.5 s: three members compared with their single runs."""
+    5,000), 0.5 s through the captured graph: three members compared with
+    their single runs."""
     # raster room for the refractory-limited maximum rate (one spike per
     # 2 ms refractory period + 0.1 ms step) over the run
     cfgs = [dict(c, record_spikes=1, record_cap=(c["n_exc"] + c["n_inh"]) * 260)
             for c in W.sweep_nets(64)]
-    bt = sdeliver.Batch(cfgs).build()
+    bt = sdeliver.Batch(cfgs).build().set_graph(True)
     bt.simulate_steps(5000)
+    assert bt.graph_launches >= 50
     n_syn = sum(m.n_syn for m in bt.members)
     assert n_syn > 3e9
     sizes = [c["n_exc"] + c["n_inh"] for c in cfgs]
