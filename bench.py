@@ -182,6 +182,46 @@ def brain_share(slices: int = 100, warmup: int = 20) -> dict:
     return out
 
 
+def sweep(slices: int = 120, warmup: int = 20) -> dict:
+    """The batched sweep: 64 independent delta networks (N 2,000-40,000, K
+    500-5,000, FP32 weights) advanced together, block sizes from the
+    autotuner (timed here, no cache), steady-state slices replayed from the
+    captured graph; aggregate events/s over all members."""
+    import torch
+
+    from paper_2109_12855_amd import sdeliver, workloads
+
+    cfgs = workloads.sweep_nets(64)
+    t0 = time.time()
+    bn, tune_us = sdeliver.autotune(cfgs, targets=(8, 16, 32, 64, 128, 256), warmup=10,
+                                    slices=20)
+    t_tune = time.time() - t0
+    bt = sdeliver.Batch([dict(c, block_neurons=b) for c, b in zip(cfgs, bn)]).build()
+    bt.set_graph(True)
+    d_min = cfgs[0]["d_min"]
+    bt.simulate_steps(warmup * d_min)
+    torch.cuda.synchronize()
+    ev0 = sum(m.stats()["events_delivered"] for m in bt.members)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    bt.simulate_steps(slices * d_min)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    ev1 = sum(m.stats()["events_delivered"] for m in bt.members)
+    out = {"workload": "sweep_64_delta_nets", "networks": len(cfgs),
+           "synapses": int(sum(m.n_syn for m in bt.members)), "slice_ms": d_min * cfgs[0]["h"],
+           "tune_s": round(t_tune, 1), "block_neurons_range": [min(bn), max(bn)],
+           "blocks": int(sum(m.sizes["n_blocks"] for m in bt.members)),
+           "slices": slices, "ms_per_slice": ms / slices,
+           "events_per_s": (ev1 - ev0) / (ms * 1e-3), "graph_replays": bt.graph_launches}
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+    return out
+
+
 def ring_errors(base: dict, forms: list, n_spikes: int = 900, seed: int = 2021) -> dict:
     """Ring contents of each BF16 storage form against the FP32 form after
     delivering the same replay list (one slice's worth of spikes): normwise
@@ -255,6 +295,8 @@ def main():
                     help="skip the 1.27e10-synapse brain-scale share measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-vs-FP32 ring error report")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the autotuned 64-network batched sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -285,6 +327,10 @@ def main():
     if not args.no_brain_share:
         share = brain_share()
         _log("brain share: " + json.dumps(share))
+    sw = None
+    if not args.no_sweep:
+        sw = sweep()
+        _log("sweep: " + json.dumps(sw))
     prec = None
     if not args.no_precision:
         prec = ring_errors(dict(base, name="precision"),
@@ -323,6 +369,7 @@ def main():
         "forms": res,
         "precision": prec,
         "brain_share": share,
+        "sweep": sw,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

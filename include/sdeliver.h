@@ -65,10 +65,13 @@ typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
  * d_min (6 bits)} plus the weight: f32 (FP32 form, 8 B) or the u16 BF16 /
  * residual bits (the BF16 forms; packed = residual there, 6 B). */
 /* Connection-table layout:
- *   SD_LAYOUT_BLOCK   block-major: the synapses into each target block of B
- *                     neurons, grouped by source; a workgroup delivers into
- *                     its block's ring window held in LDS.  For networks
- *                     whose sources each reach many targets per block.
+ *   SD_LAYOUT_BLOCK   block-major: the synapses from each source into each
+ *                     target block of B neurons form one segment; segments
+ *                     are stored source by source (a spike's segments for
+ *                     consecutive blocks are adjacent), and a workgroup
+ *                     delivers its block's segments into the block's ring
+ *                     window held in LDS.  For networks whose sources each
+ *                     reach many targets per block.
  *   SD_LAYOUT_SOURCE  source-major: each source's synapses to all local
  *                     targets form one contiguous segment (as in the
  *                     paper's per-process table, Sec. 3.1).  A delivery
@@ -235,9 +238,9 @@ sd_status sd_export_connections(sd_ctx* ctx, int64_t* h_row, int32_t* h_tgt, uin
  * block-major layout only (SD_EUNSUPPORTED otherwise), as is
  * sd_export_block */
 sd_status sd_export_segments(sd_ctx* ctx, int64_t src, int64_t* h_start, int64_t* h_len);
-/* the synapses into target block b, source-major: h_row[n_src+1] (relative
- * to the block's first synapse), then h_tgt/h_dly/h_w of *n_out synapses
- * (h_tgt == NULL: only h_row and *n_out are written) */
+/* the synapses into target block b, source by source: h_row[n_src+1] (the
+ * offsets of each source's segment in the output), then h_tgt/h_dly/h_w of
+ * *n_out synapses (h_tgt == NULL: only h_row and *n_out are written) */
 sd_status sd_export_block(sd_ctx* ctx, int32_t b, int64_t* h_row, int32_t* h_tgt, uint8_t* h_dly,
                           float* h_w, int64_t* n_out);
 /* host-side tables as used by the device: w_e/w_i[65536] (decoded FP32),

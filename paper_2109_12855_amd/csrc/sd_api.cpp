@@ -416,14 +416,6 @@ sd_status block_major_fits(const sd_config* c, Layout* L, std::string* why) {
     *why = "packed form needs (d_max - d_min + 1) * block_neurons <= 65536";
     return SD_EUNSUPPORTED;
   }
-  // a block's synapses are read through buffer resources whose "nothing to
-  // load" offset (element 2^28) must lie past the end: at most 2^28
-  // synapses and 2^30 record bytes per block
-  if ((int64_t)L->B * K > (1LL << 28) ||
-      (int64_t)L->B * K * (c->wform == SD_W_FP32 ? 8 : 4) > (1LL << 30)) {
-    *why = "a target block holds more than 2^28 synapses or 1 GiB; lower block_neurons";
-    return SD_EUNSUPPORTED;
-  }
   if (slice_lds_bytes(L->B, c->d_min, c->d_max) > 160 * 1024) {
     *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
     return SD_EUNSUPPORTED;
@@ -527,8 +519,8 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_cursor = take((size_t)L->M * ptr);
   L->off_seg = take(L->sm ? 0 : (size_t)L->n_src * L->NB * 8);
   L->off_tiles = take((size_t)L->n_tiles * ptr);
-  L->off_syn = take((size_t)L->n_syn * L->rec_bytes);
-  L->off_dly = take((size_t)L->n_syn * L->dly_bytes);
+  L->off_syn = take(std::max<size_t>((size_t)L->n_syn * L->rec_bytes, 16));  // record 0 always readable
+  L->off_dly = take(std::max<size_t>((size_t)L->n_syn * L->dly_bytes, 16));
   L->off_V = take((size_t)L->N * 4);
   L->off_y1 = take((size_t)L->N * 4);
   L->off_y2 = take((size_t)L->N * 4);
@@ -1583,7 +1575,8 @@ sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8
   h_row[0] = 0;
   for (int64_t s = 0; s < S; ++s) {
     int64_t deg = 0;
-    for (int32_t b = 0; b < c->NB; ++b) deg += rp[(size_t)(b * S + s + 1)] - rp[(size_t)(b * S + s)];
+    for (int32_t b = 0; b < c->NB; ++b)
+      deg += rp[(size_t)(s * c->NB + b + 1)] - rp[(size_t)(s * c->NB + b)];
     h_row[s + 1] = h_row[s] + deg;
   }
   if (!h_tgt && !h_dly && !h_w) return SD_OK;
@@ -1599,7 +1592,7 @@ sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8
     int64_t at = h_row[s];
     const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
     for (int32_t b = 0; b < c->NB; ++b) {
-      for (uint32_t e = rp[(size_t)(b * S + s)]; e < rp[(size_t)(b * S + s + 1)]; ++e, ++at) {
+      for (uint32_t e = rp[(size_t)(s * c->NB + b)]; e < rp[(size_t)(s * c->NB + b + 1)]; ++e, ++at) {
         int32_t t;
         float w;
         uint8_t d;
@@ -1620,7 +1613,7 @@ sd_status sd_export_segments(sd_ctx* c, int64_t src, int64_t* h_start, int64_t* 
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int32_t b = 0; b < c->NB; ++b) {
     uint32_t p[2];
-    HIP_TRY(c, hipMemcpy(p, c->row + (size_t)b * c->n_src + src, 8, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(p, c->row + (size_t)src * c->NB + b, 8, hipMemcpyDeviceToHost));
     h_start[b] = p[0];
     h_len[b] = (int64_t)p[1] - p[0];
   }
@@ -1669,24 +1662,41 @@ sd_status sd_export_block(sd_ctx* c, int32_t b, int64_t* h_row, int32_t* h_tgt, 
   if (c->sm) return fail(c, SD_EUNSUPPORTED, "source-major layout has no block regions");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const int64_t S = c->n_src;
-  std::vector<uint32_t> rp((size_t)S + 1);
-  HIP_TRY(c, hipMemcpy(rp.data(), c->row + (size_t)b * S, rp.size() * 4, hipMemcpyDeviceToHost));
-  for (int64_t s = 0; s <= S; ++s) h_row[s] = (int64_t)rp[(size_t)s] - rp[0];
+  // the block's (start, count) column of the segment pointers
+  std::vector<uint2> col((size_t)S);
+  HIP_TRY(c, hipMemcpy2D(col.data(), sizeof(uint2), c->seg + b, (size_t)c->NB * sizeof(uint2),
+                         sizeof(uint2), (size_t)S, hipMemcpyDeviceToHost));
+  h_row[0] = 0;
+  for (int64_t s = 0; s < S; ++s) h_row[s + 1] = h_row[s] + col[(size_t)s].y;
   const int64_t tot = h_row[S];
   if (n_out) *n_out = tot;
   if (!h_tgt || tot == 0) return SD_OK;
   const sd_config& g = c->cfg;
   const int rb = g.wform == SD_W_FP32 ? 8 : 4;
+  const bool has_dly = g.wform != SD_W_BF16_PACKED;
+  // gather the block's segments source by source on the device
+  int64_t* d_off = nullptr;
+  char* d_out = nullptr;
+  hipError_t e = hipMalloc((void**)&d_off, (size_t)S * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_out, (size_t)tot * (rb + 1));
+  if (e == hipSuccess) e = hipMemcpy(d_off, h_row, (size_t)S * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_gather_block(c->stream, c->seg, S, c->NB, b, d_off, c->syn,
+                            has_dly ? c->syn_dly : nullptr, rb, d_out,
+                            has_dly ? (uint8_t*)(d_out + (size_t)tot * rb) : nullptr);
   std::vector<uint8_t> rec((size_t)tot * rb), dl((size_t)tot);
-  HIP_TRY(c, hipMemcpy(rec.data(), (char*)c->syn + (size_t)rp[0] * rb, rec.size(),
-                       hipMemcpyDeviceToHost));
-  if (g.wform != SD_W_BF16_PACKED)
-    HIP_TRY(c, hipMemcpy(dl.data(), c->syn_dly + rp[0], dl.size(), hipMemcpyDeviceToHost));
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(rec.data(), d_out, rec.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && has_dly)
+    e = hipMemcpy(dl.data(), d_out + (size_t)tot * rb, dl.size(), hipMemcpyDeviceToHost);
+  if (d_off) (void)hipFree(d_off);
+  if (d_out) (void)hipFree(d_out);
+  if (e != hipSuccess) return fail(c, SD_EHIP, "block export failed: %s", hipGetErrorString(e));
   for (int64_t s = 0; s < S; ++s) {
     const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
-    for (int64_t e = h_row[s]; e < h_row[s + 1]; ++e)
-      decode_record(g, rec.data(), dl.data(), (uint32_t)e, b, c->B, mu, &h_tgt[e], &h_w[e],
-                    &h_dly[e]);
+    for (int64_t k = h_row[s]; k < h_row[s + 1]; ++k)
+      decode_record(g, rec.data(), dl.data(), (uint32_t)k, b, c->B, mu, &h_tgt[k], &h_w[k],
+                    &h_dly[k]);
   }
   return SD_OK;
 }

@@ -101,7 +101,7 @@ struct BuildArgs {
   int64_t src_e_n, src_i_n, src_i_base;
   int32_t d_lo, n_dly;
   uint64_t seed;
-  uint32_t* row;           // counts, then exclusive scan (block-major)
+  uint32_t* row;           // (src, block) counts, then exclusive scan (block-major)
   uint32_t* cursor;        // fill cursors (copy of row)
   uint2* seg;              // source-major (start, count) pairs
   // source-major layout
@@ -169,6 +169,9 @@ hipError_t launch_scan(hipStream_t s, uint32_t* data, int64_t n, uint32_t* tile_
                        int64_t n_tiles_cap);
 hipError_t launch_fill(hipStream_t s, const BuildArgs& a);
 hipError_t launch_seg_pairs(hipStream_t s, const BuildArgs& a);
+hipError_t launch_gather_block(hipStream_t s, const uint2* seg, int64_t n_src, int32_t NB,
+                               int32_t b, const int64_t* dst_off, const void* syn,
+                               const uint8_t* dly, int32_t rec_bytes, void* out, uint8_t* out_dly);
 // one fused slice of a batch: workgroup gx serves block map[gx].y of
 // network map[gx].x, arguments in device memory
 hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_map,

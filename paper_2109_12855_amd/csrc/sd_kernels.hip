@@ -12,14 +12,16 @@
 //   later slices are written to the ring in HBM.
 //
 // Build (once, untimed, Sec. 2.2):
-//   k_count / scan / k_fill lay out the block-major table: the synapses into
-//   target block b occupy one contiguous region, ordered by source, and
-//   segment (src, b) holds those from src in (target, draw) order.  A
-//   workgroup therefore only ever reads its own block's region, which keeps
-//   its address translations local.  k_fill ranks equal sources inside each
-//   chunk of draws with an LDS bitonic sort, so the layout is deterministic.
-//   k_seg_pairs then stores the segment pointers source-major, as (start,
-//   count) pairs: the blocks resolving one spike read neighbouring words.
+//   k_count / scan / k_fill lay out the block-major table: segment (src, b)
+//   holds the synapses from src into target block b in (target, draw) order,
+//   and the segments are stored source by source, so one spike's segments
+//   for blocks 0, 1, 2, ... lie next to each other.  The blocks walking a
+//   spike then read neighbouring pieces of one row of the table (shared
+//   lines, open DRAM pages) rather than a piece of each block's own region.
+//   k_fill ranks equal sources inside each chunk of draws with an LDS
+//   bitonic sort, so the layout is deterministic.  k_seg_pairs stores the
+//   segment pointers as (start, count) pairs in the same order: the blocks
+//   resolving one spike read neighbouring words.
 #include <hip/hip_runtime.h>
 
 #include "sd_internal.h"
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(256) k_count(BuildArgs a) {
   const int32_t b = (int32_t)(j / a.B);
   for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
     const Draw d = draw_synapse(a, j, k);
-    atomicAdd(&a.row[(int64_t)b * a.n_src + d.src], 1u);
+    atomicAdd(&a.row[(int64_t)d.src * a.NB + b], 1u);
   }
 }
 
@@ -227,7 +229,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(T* data, int64_t n,
 // (target, k) order, kFillChunk at a time; equal sources inside a chunk are
 // ranked by an LDS bitonic sort of (src, position) keys, so each segment
 // receives its synapses in draw order.  Only workgroup b touches the cursors
-// of column b.
+// (src, b) of its block.
 __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
   __shared__ uint64_t keys[kFillChunk];
   __shared__ uint32_t meta[kFillChunk];  // widx | inh << 16 | dly << 24
@@ -273,7 +275,7 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
       const int idx = (int)(key & 2047);
       int rank = 0;
       while (p - rank - 1 >= 0 && (uint32_t)(keys[p - rank - 1] >> 11) == src) ++rank;
-      const int64_t cell = (int64_t)b * a.n_src + src;
+      const int64_t cell = (int64_t)src * a.NB + b;
       const int64_t pos = (int64_t)a.cursor[cell] + rank;
       const uint32_t m = meta[idx];
       const uint32_t widx = m & 0xffffu, inh = (m >> 16) & 1u, dly = m >> 24;
@@ -302,22 +304,37 @@ __global__ void __launch_bounds__(kFillThreads) k_fill(BuildArgs a) {
       if (last) {
         int run = 1;
         while (p - run >= 0 && (uint32_t)(keys[p - run] >> 11) == src) ++run;
-        a.cursor[(int64_t)b * a.n_src + src] += (uint32_t)run;
+        a.cursor[(int64_t)src * a.NB + b] += (uint32_t)run;
       }
     }
     __syncthreads();
   }
 }
 
-// Source-major segment pointers: seg[s * NB + b] = (start, count) of the
-// synapses from s into block b, from the block-major scan.
+// Segment pointers: seg[s * NB + b] = (start, count) of the synapses from s
+// into block b, from the scan of the (s, b) counts.
 __global__ void k_seg_pairs(const uint32_t* row, int64_t n_src, int32_t NB, uint2* seg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_src * NB) return;
-  const int64_t s = i / NB;
-  const int64_t b = i - s * NB;
-  const uint32_t lo = row[b * n_src + s];
-  seg[i] = make_uint2(lo, row[b * n_src + s + 1] - lo);
+  const uint32_t lo = row[i];
+  seg[i] = make_uint2(lo, row[i + 1] - lo);
+}
+
+// Block b's segments gathered source by source (export): dst_off[s] is the
+// first output record of source s.
+__global__ void k_gather_block(const uint2* seg, int64_t n_src, int32_t NB, int32_t b,
+                               const int64_t* dst_off, const void* syn, const uint8_t* dly,
+                               int32_t rec_bytes, void* out, uint8_t* out_dly) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  const uint2 sg = seg[s * NB + b];
+  const int64_t o = dst_off[s];
+  for (uint32_t k = 0; k < sg.y; ++k) {
+    const uint64_t e = (uint64_t)sg.x + k;
+    if (rec_bytes == 8) ((uint64_t*)out)[o + k] = ((const uint64_t*)syn)[e];
+    else ((uint32_t*)out)[o + k] = ((const uint32_t*)syn)[e];
+    if (dly) out_dly[o + k] = dly[e];
+  }
 }
 
 // Source-major layout: per-source histogram, then a fill that appends each
@@ -620,27 +637,28 @@ template <> struct SynGroup<WF_FP32> { static constexpr int n = 16; };
 template <> struct SynGroup<WF_PACKED> { static constexpr int n = 32; };
 constexpr int kMaxGroup = 32;
 
-// A record through buffer resources over one block's records and delays:
-// element index i, or kOobIndex for a lane or slot with nothing to load:
-// blocks hold at most 2^28 synapses and 2^30 record bytes (checked at
-// creation), so that offset is out of range and the load returns zero
-// without reading memory.
+// Binned records (source-major layout) are read through a buffer resource
+// over one block's bin area: element index i, or kOobIndex for a lane or
+// slot with nothing to load (that offset lies past the area, checked at
+// creation, so the load returns zero without reading memory).
 constexpr uint32_t kOobIndex = 1u << 28;
 constexpr int kBufWord3 = 0x00020000;  // gfx9 buffer resource: 32-bit dword format
 
+// Record i of the block-major table (index 0 for a lane or slot with
+// nothing to load: the table always holds a record there, the value is
+// not used).
 template <int WF>
-__device__ __forceinline__ SynRaw<WF> syn_fetch_buf(__amdgpu_buffer_rsrc_t rs,
-                                                    __amdgpu_buffer_rsrc_t rd, uint32_t i) {
+__device__ __forceinline__ SynRaw<WF> syn_fetch(const void* syn, const uint8_t* dly, uint32_t i) {
   SynRaw<WF> x;
   if constexpr (WF == WF_FP32) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(i * 8u), 0, 0);
-    x.r = ((uint64_t)v[1] << 32) | (uint32_t)v[0];
-    x.d = __builtin_amdgcn_raw_buffer_load_b8(rd, (int)i, 0, 0);
+    const uint2 v = ((const uint2*)syn)[i];
+    x.r = ((uint64_t)v.y << 32) | v.x;
+    x.d = dly[i];
   } else if constexpr (WF == WF_PACKED) {
-    x.r = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0);
+    x.r = ((const uint32_t*)syn)[i];
   } else {
-    x.r = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0);
-    x.d = __builtin_amdgcn_raw_buffer_load_b8(rd, (int)i, 0, 0);
+    x.r = ((const uint32_t*)syn)[i];
+    x.d = dly[i];
   }
   return x;
 }
@@ -924,15 +942,6 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     const int64_t rot = total > 0 ? ((int64_t)b * 7919) % total : 0;
     constexpr int G = SynGroup<WF>::n;
     __shared__ int s_next;  // next unclaimed spike of the chunk
-    // this block's synapses: [j0 * K, (j0 + nb) * K) (fixed in-degree)
-    const uint32_t reg_lo = (uint32_t)(j0 * a.K);
-    const uint32_t reg_n = (uint32_t)((int64_t)nb * a.K);
-    constexpr uint32_t rec_bytes = (WF == WF_FP32) ? 8u : 4u;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)((const unsigned char*)a.syn + (size_t)reg_lo * rec_bytes), 0,
-        (int)(reg_n * rec_bytes), kBufWord3);
-    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(a.syn_dly ? a.syn_dly + reg_lo : nullptr), 0, (int)reg_n, kBufWord3);
     uint64_t ev = 0;
     for (int64_t c0 = 0; c0 < total; c0 += kSliceThreads) {
       const int n_c = (int)((total - c0) < kSliceThreads ? (total - c0) : kSliceThreads);
@@ -944,12 +953,12 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         const uint32_t ent = a.in_list[ir];
         const uint32_t src = ent >> 5;
         const int lag = (int)(ent & 31u);
-        uint2 sg = make_uint2(reg_lo, 0u);
+        uint2 sg = make_uint2(0u, 0u);
         if (lag < Dmin && (int64_t)src < a.n_src) sg = a.seg[(int64_t)src * a.NB + b];
         else atomicOr(a.overflow, 4);
         const uint32_t len = sg.y;
         ev += (uint64_t)len;
-        desc[tid] = make_uint2(sg.x - reg_lo, len);
+        desc[tid] = sg;
         meta[tid] = ((uint32_t)(lag * B) << 7) | (len < 65u ? len : 65u) |
                     (((int64_t)src >= a.src_e_end) ? 0x80000000u : 0u);
       }
@@ -958,8 +967,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       // (2) waves take groups of G spikes from a shared counter until the
       // chunk is done (a wave slowed by issue priority or memory latency
       // simply takes fewer groups).  G loads issue back to back (lanes past
-      // a segment's end and slots past the chunk load nothing: their buffer
-      // offset is out of range), then the adds; the group bound is uniform.
+      // a segment's end and slots past the chunk read record 0, unused),
+      // then the adds; the group bound is uniform.
       for (;;) {
         int g0 = 0;
         if (lane == 0)
@@ -974,7 +983,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           // the start also enters the predicate, so both halves are read
           // unconditionally (no per-slot branch around the LDS read)
           const bool on = (u < n_here) & (lane < (int)d.y) & (d.x != 0xffffffffu);
-          raw[u] = syn_fetch_buf<WF>(rs, rd, on ? d.x + (uint32_t)lane : kOobIndex);
+          raw[u] = syn_fetch<WF>(a.syn, a.syn_dly, on ? d.x + (uint32_t)lane : 0u);
         }
         // ALU work while the loads are in flight
         if (rounds_done < n_rounds) drive_round(rounds_done++);
@@ -1014,7 +1023,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
             for (int e0 = 64; e0 < sl; e0 += 64) {
               const bool on = lane + e0 < sl;
               const SynRaw<WF> x =
-                  syn_fetch_buf<WF>(rs, rd, on ? d.x + (uint32_t)(e0 + lane) : kOobIndex);
+                  syn_fetch<WF>(a.syn, a.syn_dly, on ? d.x + (uint32_t)(e0 + lane) : 0u);
               if (on) {
                 int slot, v;
                 syn_decode<WF>(x, (int32_t)j0, Dmin, B, inh ? a.wm0_i : a.wm0_e,
@@ -1385,6 +1394,14 @@ hipError_t launch_bin(hipStream_t s, const BinArgs& a, int32_t P, size_t lds, bo
 
 hipError_t launch_fill(hipStream_t s, const BuildArgs& a) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)a.NB), dim3(kFillThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_block(hipStream_t s, const uint2* seg, int64_t n_src, int32_t NB,
+                               int32_t b, const int64_t* dst_off, const void* syn,
+                               const uint8_t* dly, int32_t rec_bytes, void* out, uint8_t* out_dly) {
+  hipLaunchKernelGGL(k_gather_block, dim3((unsigned)((n_src + 255) / 256)), dim3(256), 0, s, seg,
+                     n_src, NB, b, dst_off, syn, dly, rec_bytes, out, out_dly);
   return hipGetLastError();
 }
 

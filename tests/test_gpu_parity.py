@@ -48,6 +48,29 @@ def test_connections_bit_exact(case, wform):
     assert np.array_equal(w.astype(np.float64), ow)
 
 
+@pytest.mark.parametrize("wform", [0, 3])
+def test_block_tables_and_segments(wform):
+    """Each block's table and each source's segment pointers agree with the
+    full export: block b holds, source by source, exactly the synapses into
+    its targets, and consecutive blocks' segments of a source are adjacent."""
+    cfg = dict(_tiny_cases()[4], wform=wform)
+    net = sdeliver.Net(cfg).build()
+    row, tgt, dly, w = net.connections()
+    B, NB = net.sizes["block_neurons"], net.sizes["n_blocks"]
+    for b in (0, NB // 2, NB - 1):
+        brow, btgt, bdly, bw = net.block_table(b)
+        for s in range(0, net.n_src, 97):
+            seg = slice(row[s], row[s + 1])
+            sel = (tgt[seg] // B) == b
+            bs = slice(brow[s], brow[s + 1])
+            assert np.array_equal(btgt[bs], tgt[seg][sel]), (b, s)
+            assert np.array_equal(bdly[bs], dly[seg][sel]) and np.array_equal(bw[bs], w[seg][sel])
+    for s in range(0, net.n_src, 131):
+        start, length = net.segments(s)
+        assert np.array_equal(start[1:], start[:-1] + length[:-1])
+        assert length.sum() == row[s + 1] - row[s]
+
+
 def test_connections_delta_1250_bit_exact():
     cfg = W.DELTA_SMALL
     net = sdeliver.Net(cfg).build()
