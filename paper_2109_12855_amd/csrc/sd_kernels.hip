@@ -631,10 +631,14 @@ template <> struct SynRaw<WF_BF16> { uint32_t r; uint32_t d; };
 template <> struct SynRaw<WF_BF16_RESID> { uint32_t r; uint32_t d; };
 template <> struct SynRaw<WF_PACKED> { uint32_t r; };
 
-// segment loads in flight per wave (register budget of the record form)
-template <int WF> struct SynGroup { static constexpr int n = 20; };
-template <> struct SynGroup<WF_FP32> { static constexpr int n = 16; };
-template <> struct SynGroup<WF_PACKED> { static constexpr int n = 32; };
+// Segments a wave takes from the chunk at a time (all loads in flight
+// before the adds).  Measured on the 112,500-neuron network (~44-synapse
+// segments): smaller groups spread a chunk's ~900 spikes more evenly over
+// the 16 waves and keep the blocks of an XCD on nearby spikes; below these
+// sizes the loads in flight no longer cover the latency.
+template <int WF> struct SynGroup { static constexpr int n = 12; };
+template <> struct SynGroup<WF_FP32> { static constexpr int n = 8; };
+template <> struct SynGroup<WF_PACKED> { static constexpr int n = 12; };
 constexpr int kMaxGroup = 32;
 
 // Binned records (source-major layout) are read through a buffer resource
@@ -935,11 +939,9 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     const int64_t total = total_raw < a.in_cap ? total_raw : a.in_cap;
     __syncthreads();  // thr / zeroing visible
 
-    // Spikes are taken in chunks of one per thread.  Each block starts at a
-    // different point of the list (the sums are exact integers, so the order
-    // is free): otherwise all blocks would read the same relative offsets of
-    // their equally sized regions at the same moment.
-    const int64_t rot = total > 0 ? ((int64_t)b * 7919) % total : 0;
+    // Spikes are taken in chunks of one per thread, in list order in every
+    // block: the blocks then read neighbouring segments of the same spikes
+    // at about the same time.
     constexpr int G = SynGroup<WF>::n;
     __shared__ int s_next;  // next unclaimed spike of the chunk
     uint64_t ev = 0;
@@ -949,8 +951,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       // the list entry, then the segment's (start, count) pair
       if (tid < n_c) {
         const int64_t i = c0 + tid;
-        const int64_t ir = (i + rot) < total ? i + rot : i + rot - total;
-        const uint32_t ent = a.in_list[ir];
+        const uint32_t ent = a.in_list[i];
         const uint32_t src = ent >> 5;
         const int lag = (int)(ent & 31u);
         uint2 sg = make_uint2(0u, 0u);
