@@ -263,6 +263,7 @@ struct sd_ctx {
   uint32_t* thr = nullptr;
   double* prop64 = nullptr;
   float* prop32 = nullptr;
+  float prop_h[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // host copy, passed by value to the slices
   unsigned long long* counters = nullptr;  // ev, spk_in, spk, rec_n
   int32_t* overflow = nullptr;
   // open-loop input schedule
@@ -609,7 +610,7 @@ SliceArgs base_args(sd_ctx* c) {
   a.y1 = c->y1;
   a.y2 = c->y2;
   a.r = c->r;
-  a.prop = c->prop32;
+  std::memcpy(a.prop, c->prop_h, sizeof a.prop);
   a.thr = c->thr;
   a.n_thr = c->n_thr;
   a.seed = g.seed;
@@ -889,6 +890,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, launch_init_state(c->stream, c->N, g.seed, g.v0_lo, g.v0_hi, c->V, c->y1, c->y2,
                                c->r));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(c->prop_h, c->prop32, sizeof c->prop_h, hipMemcpyDeviceToHost));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max);

@@ -59,7 +59,7 @@ struct SliceArgs {
   float* y1;
   float* y2;
   int32_t* r;
-  const float* prop;       // P11 P21 P22 P31 P32 P33 P30*I_e in_scale (FP32)
+  float prop[8];           // P11 P21 P22 P31 P32 P33 P30*I_e in_scale (FP32, by value)
   const uint32_t* thr;     // Poisson-drive thresholds
   int32_t n_thr;
   uint64_t seed;
