@@ -182,6 +182,21 @@ def brain_share(slices: int = 100, warmup: int = 20) -> dict:
     return out
 
 
+def short_delay(slices: int = 5000, warmup: int = 1000) -> dict:
+    """The 112,500-neuron net with delays of 1..20 steps (packed records):
+    one-step slices, ten times as many per simulated second, each with a
+    tenth of the spikes -- the per-slice cost dominates."""
+    from paper_2109_12855_amd import workloads
+
+    cfg = dict(workloads.ALPHA_112K_SHORT_DELAY)
+    r = run_form(cfg, slices, warmup)
+    return {"workload": "alpha_112500_k11250_dmin_0.1ms", "slice_ms": cfg["h"] * cfg["d_min"],
+            "slices": slices, "us_per_slice": r["kernel_ms"] * 1e3,
+            "events_per_slice": r["events_per_step"], "spikes_per_slice": r["spikes_per_step"],
+            "events_per_s": r["events_per_s"], "alg_gbs": r["kernel_gbs"],
+            "roofline_frac": r["kernel_gbs"] / HBM_PEAK_GBS, "rate_hz": r["rate_hz"]}
+
+
 def sweep(slices: int = 120, warmup: int = 20) -> dict:
     """The batched sweep: 64 independent delta networks (N 2,000-40,000, K
     500-5,000, FP32 weights) advanced together, block sizes from the
@@ -295,6 +310,8 @@ def main():
                     help="skip the 1.27e10-synapse brain-scale share measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-vs-FP32 ring error report")
+    ap.add_argument("--no-short-delay", action="store_true",
+                    help="skip the one-step-slice (d_min = 0.1 ms) workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the autotuned 64-network batched sweep")
     ap.add_argument("--copy-probe", action="store_true",
@@ -327,6 +344,10 @@ def main():
     if not args.no_brain_share:
         share = brain_share()
         _log("brain share: " + json.dumps(share))
+    sd = None
+    if not args.no_short_delay:
+        sd = short_delay()
+        _log("short delay: " + json.dumps(sd))
     sw = None
     if not args.no_sweep:
         sw = sweep()
@@ -369,6 +390,7 @@ def main():
         "forms": res,
         "precision": prec,
         "brain_share": share,
+        "short_delay": sd,
         "sweep": sw,
         "roofline": roof,
         "cpu_baseline": cpu,

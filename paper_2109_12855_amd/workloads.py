@@ -92,7 +92,15 @@ ALPHA_BRAIN_SHARE = dict(
     t_sim_ms=500.0,
 )
 
-WORKLOADS = {w["name"]: w for w in (DELTA_SMALL, ALPHA_112K, ALPHA_112K_BF16, ALPHA_BRAIN_SHARE)}
+# Short minimum delay: the 112,500-neuron net with delays uniform over 1..20
+# steps (0.1-2 ms), so a slice is a single 0.1 ms step -- ten times as many
+# slices per simulated second, each delivering a tenth of the spikes, which
+# stresses the per-slice cost (packed 4-byte records).
+ALPHA_112K_SHORT_DELAY = dict(ALPHA_112K, name="alpha_112500_dmin1_packed", wform=3,
+                              d_lo=1, d_hi=20, d_min=1, d_max=20)
+
+WORKLOADS = {w["name"]: w for w in (DELTA_SMALL, ALPHA_112K, ALPHA_112K_BF16, ALPHA_BRAIN_SHARE,
+                                    ALPHA_112K_SHORT_DELAY)}
 
 
 def tiny(model: int = 0, n: int = 40, k: int = 8, seed: int = 7, d_lo: int | None = None,
