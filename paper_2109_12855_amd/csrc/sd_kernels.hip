@@ -693,6 +693,14 @@ __device__ __forceinline__ float from_fixed(long long q, double inv) {
   return (float)((double)q * inv);
 }
 
+// A thread keeps the staged HBM ring rows of its own neuron in registers
+// when every neuron has its own thread and a slice has at most this many
+// steps; otherwise they are staged in LDS.
+constexpr int kRegRows = 16;
+__host__ __device__ inline bool staged_in_regs(int B, int Dmin) {
+  return B <= kSliceThreads && Dmin <= kRegRows;
+}
+
 // LDS layout of a slice workgroup (byte offsets, 16-byte aligned pieces)
 struct SliceLds {
   size_t win, carry, dcnt, mask, thr, scr, desc, meta, total;
@@ -702,7 +710,7 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_ro
   SliceLds L;
   size_t o = 0;
   L.win = o;   o = up(o + (size_t)win_rows * B * 8);    // int64 ring window
-  L.carry = o; o = up(o + (size_t)Dmin * B * 4);        // staged HBM rows (FP32)
+  L.carry = o; o = up(o + (staged_in_regs(B, Dmin) ? 0 : (size_t)Dmin * B * 4));  // staged HBM rows
   L.dcnt = o;  o = up(o + (size_t)Dmin * B);            // Poisson-drive counts (u8)
   L.mask = o;  o = up(o + (size_t)Dmin * (B / 32) * 4); // spike bitmask
   L.thr = o;   o = up(o + (size_t)kMaxThr * 4);         // drive thresholds
@@ -779,7 +787,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // Carried ring rows (deliveries of earlier slices) and this thread's
   // neuron state are loaded into registers now; they arrive while the
   // spikes are delivered.
-  constexpr int kRows = 16;
+  constexpr int kRows = kRegRows;
   int rows = 0;
   if (a.n_upd > 0) {
     int64_t t_hi = a.t_upd + a.n_upd;
@@ -787,16 +795,20 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     rows = (int)(t_hi > a.t_upd ? t_hi - a.t_upd : 0);
   }
   const int r0 = (int)(a.t_upd % a.L);
-  const bool fast = rows > 0 && rows <= kRows && nb <= kSliceThreads;
+  const bool regs = staged_in_regs(B, Dmin);  // rows <= n_upd <= Dmin <= kRows
+  const bool fast = regs && rows > 0;
   const int n_own = tid < nb ? tid : nb - 1;  // in-bounds neuron of this thread
   float stage[kRows];
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) stage[q] = 0.f;
   if (fast) {
 #pragma unroll
     for (int q = 0; q < kRows; ++q) {
       int rr = r0 + (q < rows ? q : 0);
       if (rr >= a.L) rr -= a.L;
       const int64_t at = (int64_t)rr * a.N + j0 + n_own;
-      stage[q] = a.rb[at];
+      const float v = a.rb[at];
+      stage[q] = q < rows ? v : 0.f;  // rows at or past rb_hi hold no earlier input
     }
   }
   float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
@@ -1052,22 +1064,14 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   }
   while (rounds_done < n_rounds) drive_round(rounds_done++);
 
-  // staged rows into LDS
-  if (a.n_upd > 0) {
-    if (fast) {
-      if (tid < nb) {
-#pragma unroll
-        for (int q = 0; q < kRows; ++q)
-          if (q < rows) carry[q * B + tid] = stage[q];
-      }
-    } else {
-      for (int i = tid; i < rows * nb; i += kSliceThreads) {
-        const int q = i / nb, n = i - q * nb;
-        int rr = r0 + q;
-        while (rr >= a.L) rr -= a.L;
-        const int64_t at = (int64_t)rr * a.N + j0 + n;
-        carry[q * B + n] = a.rb[at];
-      }
+  // staged rows into LDS (when they are not kept in registers)
+  if (a.n_upd > 0 && !regs) {
+    for (int i = tid; i < rows * nb; i += kSliceThreads) {
+      const int q = i / nb, n = i - q * nb;
+      int rr = r0 + q;
+      while (rr >= a.L) rr -= a.L;
+      const int64_t at = (int64_t)rr * a.N + j0 + n;
+      carry[q * B + n] = a.rb[at];
     }
     // rows at or past rb_hi hold no earlier input
     for (int i = tid; i < (a.n_upd - rows) * nb; i += kSliceThreads) {
@@ -1150,7 +1154,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           const int s = s0 + q;
           float in = 0.f, dr = 0.f;
           if (s < a.n_upd) {
-            in = carry[s * B + n];
+            in = regs ? stage[q] : carry[s * B + n];  // regs: one pass (s == q), n == tid
             dr = (float)dcnt[s * B + n] * a.drive_w;
             if (a.do_deliver && qw + s >= 0 && qw + s < a.Dmax)
               in += from_fixed(win[(qw + s) * B + n], inv);
