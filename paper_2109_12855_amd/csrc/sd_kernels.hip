@@ -384,16 +384,19 @@ __global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
 // atomics are involved.  A region that fills up sends further events to the
 // fixed-point spill rows with global atomics and flags the block.
 struct BinLds {
-  size_t stage, dst, cnt, cur, pre, lo, mt, scr, total;
+  size_t stage, dst, cc, pre, lo, mt, scr, total;
 };
 __host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   BinLds L;
   size_t o = 0;
-  L.stage = o; o = up(o + (size_t)U * kBinThreads * (w8 ? 8 : 4));  // sorted chunk
-  L.dst = o;   o = up(o + (size_t)U * kBinThreads * 4);  // destination of each sorted record
-  L.cnt = o;   o = up(o + (size_t)(NB + 1) * 4);  // counts, then bin starts
-  L.cur = o;   o = up(o + (size_t)NB * 4);        // records in each region so far
+  // sorted chunk: {record, destination} (4-byte records) or {record, FP32
+  // weight} with the destinations apart (8-byte records)
+  L.stage = o; o = up(o + (size_t)U * kBinThreads * 8);
+  L.dst = o;   o = up(o + (w8 ? (size_t)U * kBinThreads * 4 : 0));
+  // per block: {count in the chunk, then the bin's start; records in this
+  // workgroup's region so far}
+  L.cc = o;    o = up(o + (size_t)(NB + 1) * 8);
   L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per spike
   L.lo = o;    o = up(o + (size_t)kBinSpikes * 8);  // segment start per spike
   L.mt = o;    o = up(o + (size_t)kBinSpikes * 4);  // lag | inhibitory << 15
@@ -414,11 +417,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   const int p = blockIdx.x, P = gridDim.x;
   const int NB = a.NB, B = a.B, U = a.U, cap = a.cap;
   const BinLds Lo = bin_lds_layout(NB, U, W8);
-  uint32_t* stage = (uint32_t*)(lds_raw + Lo.stage);
   uint2* stage2 = (uint2*)(lds_raw + Lo.stage);
   uint32_t* dst = (uint32_t*)(lds_raw + Lo.dst);
-  uint32_t* cnt = (uint32_t*)(lds_raw + Lo.cnt);
-  uint32_t* cur = (uint32_t*)(lds_raw + Lo.cur);
+  uint2* cc = (uint2*)(lds_raw + Lo.cc);
   unsigned long long* pre = (unsigned long long*)(lds_raw + Lo.pre);
   unsigned long long* lo = (unsigned long long*)(lds_raw + Lo.lo);
   uint32_t* mt = (uint32_t*)(lds_raw + Lo.mt);
@@ -429,8 +430,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
   if (total < 0) total = 0;
   const int64_t s_lo = total * p / P, s_hi = total * (p + 1) / P;
-  for (int i = tid; i <= NB; i += kBinThreads) cnt[i] = 0u;
-  for (int i = tid; i < NB; i += kBinThreads) cur[i] = 0u;
+  for (int i = tid; i <= NB; i += kBinThreads) cc[i] = make_uint2(0u, 0u);
   unsigned long long ev = 0;
   const uint32_t tmask = (1u << kTgtBits) - 1u;
   const uint32_t region0 = (uint32_t)p * (uint32_t)cap;  // this workgroup's region in a block's area
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           const uint32_t r = (uint32_t)(q * B + off) | ((m & 32u) << 10);
           if constexpr (W8) rec8[u] = r;
           else wbr[u] = r | (wbr[u] << 16);
-          const uint32_t rank = __hip_atomic_fetch_add(&cnt[blk], 1u, __ATOMIC_RELAXED,
+          const uint32_t rank = __hip_atomic_fetch_add(&cc[blk].x, 1u, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
           tdk[u] = ((uint32_t)blk << 16) | rank;
         }
@@ -540,15 +540,15 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
         const int per = (NB + kBinThreads - 1) / kBinThreads;
         const int i0 = tid * per, i1 = (i0 + per) < NB ? i0 + per : NB;
         uint32_t sum = 0;
-        for (int i = i0; i < i1; ++i) sum += cnt[i];
+        for (int i = i0; i < i1; ++i) sum += cc[i].x;
         uint32_t n_chunk;
         uint32_t run = block_excl_scan<uint32_t>(sum, scr32, n_chunk);
         for (int i = i0; i < i1; ++i) {
-          const uint32_t c = cnt[i];
-          cnt[i] = run;
+          const uint32_t c = cc[i].x;
+          cc[i].x = run;
           run += c;
         }
-        if (tid == 0) cnt[NB] = n_chunk;
+        if (tid == 0) cc[NB].x = n_chunk;
       }
       __syncthreads();
       // (4) scatter into bin order, with each record's destination: its
@@ -559,11 +559,16 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       for (int u = 0; u < UM; ++u) {
         if (tdk[u] != 0xffffffffu) {
           const uint32_t blk = tdk[u] >> 16;
-          const uint32_t at = cnt[blk] + (tdk[u] & 0xffffu);
-          const uint32_t pos = cur[blk] + (tdk[u] & 0xffffu);
-          if constexpr (W8) stage2[at] = make_uint2(rec8[u], wbr[u]);
-          else stage[at] = wbr[u];
-          dst[at] = pos < (uint32_t)cap ? blk * area + region0 + pos : kNoDst | blk;
+          const uint2 c = cc[blk];
+          const uint32_t at = c.x + (tdk[u] & 0xffffu);
+          const uint32_t pos = c.y + (tdk[u] & 0xffffu);
+          const uint32_t d = pos < (uint32_t)cap ? blk * area + region0 + pos : kNoDst | blk;
+          if constexpr (W8) {
+            stage2[at] = make_uint2(rec8[u], wbr[u]);
+            dst[at] = d;
+          } else {
+            stage2[at] = make_uint2(wbr[u], d);
+          }
         }
       }
       __syncthreads();
@@ -572,19 +577,19 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       // (5) every thread stores sorted records f, f + 1024, ...: a bin's run
       // goes to consecutive addresses (coalesced stores of ~E_c / NB
       // records), then the fills advance
-      const uint32_t n_chunk = cnt[NB];
+      const uint32_t n_chunk = cc[NB].x;
 #pragma unroll
       for (int u = 0; u < UM; ++u) {
         const uint32_t i = (uint32_t)(u * kBinThreads + tid);
         if (i < n_chunk) {
-          const uint32_t d = dst[i];
-          uint32_t r, wx = 0u;
+          const uint2 x = stage2[i];
+          const uint32_t r = x.x;
+          uint32_t d, wx = 0u;
           if constexpr (W8) {
-            const uint2 x = stage2[i];
-            r = x.x;
             wx = x.y;
+            d = dst[i];
           } else {
-            r = stage[i];
+            d = x.y;
           }
           if (!(d & kNoDst)) {
             if constexpr (W8) ((uint2*)a.bins)[d] = make_uint2(r, wx);
@@ -605,15 +610,15 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           }
         }
       }
-      for (int b = tid; b < NB; b += kBinThreads) cur[b] += cnt[b + 1] - cnt[b];
+      for (int b = tid; b < NB; b += kBinThreads) cc[b].y += cc[b + 1].x - cc[b].x;
       __syncthreads();
-      for (int i = tid; i <= NB; i += kBinThreads) cnt[i] = 0u;
+      for (int i = tid; i <= NB; i += kBinThreads) cc[i].x = 0u;
       __syncthreads();
     }
   }
   // record counts of this workgroup's regions
   for (int b = tid; b < NB; b += kBinThreads)
-    a.bin_cnt[(size_t)b * P + p] = cur[b] < (uint32_t)cap ? cur[b] : (uint32_t)cap;
+    a.bin_cnt[(size_t)b * P + p] = cc[b].y < (uint32_t)cap ? cc[b].y : (uint32_t)cap;
   if (tid == 0) {
     if (ev) atomicAdd(a.ev_count, ev);
     if (p == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
