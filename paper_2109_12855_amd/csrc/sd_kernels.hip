@@ -1,15 +1,22 @@
 // sd_kernels.hip -- gfx950 kernels of the spike-delivery library.
 //
 // Hot path (one fused launch per slice of d_min steps):
-//   k_slice: a workgroup owns one block of B target neurons.  It first walks
-//   the target segments of every spike of the completed slice (Alg. REF,
-//   Sec. 3.2) and adds each weight into an LDS copy of its block's ring
-//   window (d_max rows x B neurons), then advances its neurons through the
-//   next slice with the exact propagators (Sec. 2.1), reading inputs straight
-//   from the LDS window, and finally compacts the new spikes with a bitmask +
-//   block scan and appends them, ordered (lag, neuron) within the block, to
-//   the slice's contiguous spike list.  Rows of the window that are due in
-//   later slices are written to the ring in HBM.
+//   k_slice1 (one network, arguments by value) / k_slice (a batch, arguments
+//   in device memory): a workgroup owns one block of B target neurons.  It
+//   first walks the target segments of every spike of the completed slice
+//   (Alg. REF, Sec. 3.2) and adds each weight into an LDS copy of its
+//   block's ring window (d_max rows x B neurons, 64-bit fixed point), then
+//   advances its neurons through the next slice with the exact propagators
+//   (Sec. 2.1), reading inputs straight from the LDS window, and finally
+//   compacts the new spikes with a bitmask + block scan and appends them,
+//   ordered (lag, neuron) within the block, to the slice's contiguous spike
+//   list.  Rows of the window that are due in later slices are written to
+//   the ring in HBM by the threads without a neuron, during the update.
+//   Source-major layout: k_bin first sorts the slice's events by target
+//   block into binned records; the slice kernel then accumulates those
+//   instead of walking segments (k_slice1<form, true>).
+//   k_shift_args moves the device-resident arguments of a captured batch
+//   graph on by one period.
 //
 // Build (once, untimed, Sec. 2.2):
 //   k_count / scan / k_fill lay out the block-major table: segment (src, b)
