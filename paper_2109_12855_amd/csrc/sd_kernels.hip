@@ -770,15 +770,24 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   uint2* desc = (uint2*)(lds_raw + Lo.desc);
   uint32_t* meta = (uint32_t*)(lds_raw + Lo.meta);
 
-  // loads whose latency the LDS zeroing below covers
+  // Loads consumed only after the first wait of the delivery below, so
+  // their latency overlaps the ring-row and state loads.  The list count
+  // is a vector load: a scalar one would make every later scalar load of an
+  // argument wait for it.
   const uint32_t thr_v = (tid < kMaxThr && tid < a.n_thr) ? a.thr[tid] : 0xffffffffu;
-  const int64_t total_raw = (!BIN && a.do_deliver) ? (int64_t)*a.in_cnt : 0;
+  const int32_t total_raw =
+      (!BIN && a.do_deliver)
+          ? __hip_atomic_load(a.in_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+          : 0;
+  // this thread's list entry of the first chunk, read within the list's
+  // capacity before its length is known
+  const uint32_t ent0 = (!BIN && a.do_deliver && tid < a.in_cap) ? a.in_list[tid] : 0u;
   uint32_t bin_len = 0;
   int spill_on = 0;
   if constexpr (BIN) {
     if (a.do_deliver) {
       if (tid < a.bin_P) bin_len = a.bin_cnt[(size_t)b * a.bin_P + tid];
-      spill_on = a.spill_flag[b];
+      spill_on = __hip_atomic_load(a.spill_flag + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 
@@ -810,6 +819,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   const bool regs = staged_in_regs(B, Dmin);  // rows <= n_upd <= Dmin <= kRows
   const bool fast = regs && rows > 0;
   const int n_own = tid < nb ? tid : nb - 1;  // in-bounds neuron of this thread
+  // Raw values: rows at or past rb_hi hold no earlier input and are masked
+  // where the update reads them, so nothing here waits for these loads.
   float stage[kRows];
 #pragma unroll
   for (int q = 0; q < kRows; ++q) stage[q] = 0.f;
@@ -818,9 +829,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     for (int q = 0; q < kRows; ++q) {
       int rr = r0 + (q < rows ? q : 0);
       if (rr >= a.L) rr -= a.L;
-      const int64_t at = (int64_t)rr * a.N + j0 + n_own;
-      const float v = a.rb[at];
-      stage[q] = q < rows ? v : 0.f;  // rows at or past rb_hi hold no earlier input
+      stage[q] = a.rb[(int64_t)rr * a.N + j0 + n_own];
     }
   }
   float sV = 0.f, sy1 = 0.f, sy2 = 0.f;
@@ -867,8 +876,10 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   int rounds_done = 0;
 
   // ---- deliver the completed slice into the LDS window (Alg. REF) -------
-  if (tid < kMaxThr) thr[tid] = thr_v;
+  // The drive thresholds go to LDS right before the first barrier, behind
+  // a wait for loads issued after theirs.
   if (BIN && a.do_deliver) {
+    if (tid < kMaxThr) thr[tid] = thr_v;
     __syncthreads();  // thr / zeroing visible
     // Work items of up to kBinSlice records of one region of this block's
     // bin area; waves take GB items at a time from a shared counter, RB
@@ -945,7 +956,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       }
     }
     // events that found their region full: fixed-point spill rows
-    if (spill_on) {
+    if (__builtin_amdgcn_readfirstlane(spill_on)) {
       for (int i = tid; i < a.Dmax * nb; i += kSliceThreads) {
         const int q = i / nb, n = i - q * nb;
         long long* cell = a.spill + (int64_t)q * a.N + j0 + n;
@@ -959,23 +970,29 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       if (tid == 0) a.spill_flag[b] = 0;
     }
   } else if (!BIN && a.do_deliver) {
-    // overflow beyond the list's capacity is flagged by its writer
-    const int64_t total = total_raw < a.in_cap ? total_raw : a.in_cap;
-    __syncthreads();  // thr / zeroing visible
-
     // Spikes are taken in chunks of one per thread, in list order in every
     // block: the blocks then read neighbouring segments of the same spikes
-    // at about the same time.
+    // at about the same time.  The barrier after a chunk's descriptors also
+    // makes the window zeroing visible to the walk.
     constexpr int G = SynGroup<WF>::n;
     __shared__ int s_next;  // next unclaimed spike of the chunk
     uint64_t ev = 0;
-    for (int64_t c0 = 0; c0 < total; c0 += kSliceThreads) {
-      const int n_c = (int)((total - c0) < kSliceThreads ? (total - c0) : kSliceThreads);
+    int64_t total = 0;
+    for (int64_t c0 = 0;; c0 += kSliceThreads) {
       // (1) every thread resolves one spike into its segment of this block:
-      // the list entry, then the segment's (start, count) pair
+      // the list entry (the first chunk's was loaded with the ring rows),
+      // then the segment's (start, count) pair
+      const int64_t i = c0 + tid;
+      uint32_t ent = ent0;
+      if (c0 > 0) ent = i < a.in_cap ? a.in_list[i] : 0u;
+      if (c0 == 0) {
+        // overflow beyond the list's capacity is flagged by its writer
+        const int64_t t = (int64_t)__builtin_amdgcn_readfirstlane(total_raw);
+        total = t < a.in_cap ? t : a.in_cap;
+      }
+      if (c0 >= total) break;
+      const int n_c = (int)((total - c0) < kSliceThreads ? (total - c0) : kSliceThreads);
       if (tid < n_c) {
-        const int64_t i = c0 + tid;
-        const uint32_t ent = a.in_list[i];
         const uint32_t src = ent >> 5;
         const int lag = (int)(ent & 31u);
         uint2 sg = make_uint2(0u, 0u);
@@ -987,6 +1004,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         meta[tid] = ((uint32_t)(lag * B) << 7) | (len < 65u ? len : 65u) |
                     (((int64_t)src >= a.src_e_end) ? 0x80000000u : 0u);
       }
+      if (c0 == 0 && tid < kMaxThr) thr[tid] = thr_v;
       if (tid == 0) s_next = 0;
       __syncthreads();
       // (2) waves take groups of G spikes from a shared counter until the
@@ -1064,6 +1082,10 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       }
       __syncthreads();  // the next chunk overwrites the descriptors
     }
+    if (total == 0) {  // no chunk stored the thresholds or made the zeroing visible
+      if (tid < kMaxThr) thr[tid] = thr_v;
+      __syncthreads();
+    }
     // events of this wave
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
@@ -1072,6 +1094,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
                              __HIP_MEMORY_SCOPE_WORKGROUP);
     if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
   } else {
+    if (tid < kMaxThr) thr[tid] = thr_v;
     __syncthreads();  // thr / zeroing visible
   }
   while (rounds_done < n_rounds) drive_round(rounds_done++);
@@ -1166,7 +1189,8 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           const int s = s0 + q;
           float in = 0.f, dr = 0.f;
           if (s < a.n_upd) {
-            in = regs ? stage[q] : carry[s * B + n];  // regs: one pass (s == q), n == tid
+            // regs: one pass (s == q), n == tid
+            in = regs ? (s < rows ? stage[q] : 0.f) : carry[s * B + n];
             dr = (float)dcnt[s * B + n] * a.drive_w;
             if (a.do_deliver && qw + s >= 0 && qw + s < a.Dmax)
               in += from_fixed(win[(qw + s) * B + n], inv);
