@@ -705,6 +705,8 @@ __device__ __forceinline__ float from_fixed(long long q, double inv) {
   return (float)((double)q * inv);
 }
 
+template <bool V> struct BoolC { static constexpr bool value = V; };
+
 // A thread keeps the staged HBM ring rows of its own neuron in registers
 // when every neuron has its own thread and a slice has at most this many
 // steps; otherwise they are staged in LDS.
@@ -800,7 +802,11 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // (thousands of same-address global atomics per launch back up the
   // memory queues of every compute unit)
   __shared__ unsigned long long s_ev;
-  if (tid == 0) s_ev = 0;
+  __shared__ long long s_zero;  // read by the update for steps outside the window
+  if (tid == 0) {
+    s_ev = 0;
+    s_zero = 0;
+  }
   // the list counter of a later slice starts at zero
   if (b == 0 && tid == 0 && a.zero_cnt) *a.zero_cnt = 0;
 
@@ -1136,20 +1142,23 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     const int n_add = (int)add_rows;
     for (int n = t0; n < nb; n += stride) {
       for (int k0 = 0; k0 < nrows; k0 += kFl) {
-        float v[kFl];
-#pragma unroll
-        for (int k = 0; k < kFl; ++k)
-          if (k0 + k < nrows) v[k] = from_fixed(win[(q0 + k0 + k) * B + n], inv);
+        // Rows past nrows are clamped to the last one, so every read is in
+        // range and none sits behind a branch: the ring loads of the rows
+        // added into issue together, and one wait covers them.
+        float v[kFl], old[kFl];
+        float* p[kFl];
 #pragma unroll
         for (int k = 0; k < kFl; ++k) {
-          if (k0 + k < nrows) {
-            int row = row0 + k0 + k;
-            if (row >= a.L) row -= a.L;  // row0 < L and nrows <= Dmax < L
-            float* p = a.rb + (int64_t)row * a.N + j0 + n;
-            if (k0 + k < n_add) *p += v[k];
-            else *p = v[k];
-          }
+          const int kk = (k0 + k < nrows) ? k0 + k : nrows - 1;
+          int row = row0 + kk;
+          if (row >= a.L) row -= a.L;  // row0 < L and nrows <= Dmax < L
+          p[k] = a.rb + (int64_t)row * a.N + j0 + n;
+          old[k] = k0 + k < n_add ? *p[k] : 0.f;
+          v[k] = from_fixed(win[(q0 + kk) * B + n], inv);
         }
+#pragma unroll
+        for (int k = 0; k < kFl; ++k)
+          if (k0 + k < nrows) *p[k] = old[k] + v[k];
       }
     }
   };
@@ -1157,7 +1166,11 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   if (a.do_deliver && split && tid >= nb) flush_rows(tid - nb, kSliceThreads - nb);
 
   // ---- update the next slice's steps (exact propagation, Sec. 2.1) -------
-  if (a.n_upd > 0) {
+  // Two compiled forms, staged rows in registers (kRegs) or in LDS: with
+  // one run-time form the compiler puts each step's read behind a branch
+  // on the (uniform) choice and waits for it there.
+  auto update = [&](auto regs_tag) {
+    constexpr bool kRegs = decltype(regs_tag)::value;
     const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
     const float P32 = a.prop[4], P33 = a.prop[5], P30Ie = a.prop[6], insc = a.prop[7];
     const double inv = a.fx_inv;
@@ -1182,44 +1195,67 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       // reads), then the steps run on registers
       constexpr int kSteps = 16;
       const int qw = (int)(a.t_upd - w_lo);  // window row of the first step
-      for (int s0 = 0; s0 < a.n_upd; s0 += kSteps) {
+      // fields used per step, read once (a read inside a step would wait
+      // for the LDS reads issued before it: both share one counter)
+      const int n_upd = a.n_upd, Dmax = a.Dmax;
+      const bool deliv = a.do_deliver != 0;
+      const float drive_w = a.drive_w;
+      const float e_l = a.e_l, v_th = a.v_th, v_reset = a.v_reset;
+      const int ref_steps = a.ref_steps, lag_upd = (int)(a.t_upd - a.t_slice0);
+      const bool delta = a.model == MODEL_DELTA;
+      for (int s0 = 0; s0 < n_upd; s0 += kSteps) {
+        // All reads at in-range rows (clamped), results masked afterwards.
+        // The scheduling barrier keeps the scheduler from pairing each read
+        // with its use, so the reads issue back to back and one wait covers
+        // them.
+        long long wq[kSteps];
+        uint32_t dc[kSteps];
+        float cv[kSteps];
+#pragma unroll
+        for (int q = 0; q < kSteps; ++q) {
+          const int s = s0 + q;
+          const bool on = s < n_upd;
+          const int sc = on ? s : 0;
+          const bool w_on = deliv & on & (qw + s >= 0) & (qw + s < Dmax);
+          // the address is chosen, not the value: a read whose value is
+          // selected by a uniform condition ends up behind a branch
+          wq[q] = *(w_on ? &win[(qw + s) * B + n] : &s_zero);
+          dc[q] = dcnt[sc * B + n];
+          if constexpr (!kRegs) cv[q] = carry[sc * B + n];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         float in_s[kSteps], dr_s[kSteps];
 #pragma unroll
         for (int q = 0; q < kSteps; ++q) {
           const int s = s0 + q;
-          float in = 0.f, dr = 0.f;
-          if (s < a.n_upd) {
-            // regs: one pass (s == q), n == tid
-            in = regs ? (s < rows ? stage[q] : 0.f) : carry[s * B + n];
-            dr = (float)dcnt[s * B + n] * a.drive_w;
-            if (a.do_deliver && qw + s >= 0 && qw + s < a.Dmax)
-              in += from_fixed(win[(qw + s) * B + n], inv);
-          }
-          in_s[q] = in;
-          dr_s[q] = dr;
+          const bool on = s < n_upd;
+          float in;
+          if constexpr (kRegs) in = s < rows ? stage[q] : 0.f;  // one pass (s == q), n == tid
+          else in = cv[q];
+          in += from_fixed(wq[q], inv);
+          in_s[q] = on ? in : 0.f;
+          dr_s[q] = on ? (float)dc[q] * drive_w : 0.f;
         }
 #pragma unroll
         for (int q = 0; q < kSteps; ++q) {
         const int s = s0 + q;
-        if (s >= a.n_upd) break;
-        const int64_t t = a.t_upd + s;
+        if (s >= n_upd) break;
         const float in = in_s[q];
         const float drive = dr_s[q];
-        if (a.model == MODEL_DELTA) {
+        if (delta) {
           if (r > 0) --r;
-          else V = a.e_l + P33 * (V - a.e_l) + P30Ie + in + drive;
+          else V = e_l + P33 * (V - e_l) + P30Ie + in + drive;
         } else {
-          if (r == 0) V = a.e_l + P31 * y1 + P32 * y2 + P33 * (V - a.e_l) + P30Ie;
+          if (r == 0) V = e_l + P31 * y1 + P32 * y2 + P33 * (V - e_l) + P30Ie;
           else --r;
           const float y2n = P21 * y1 + P22 * y2;
           y1 = P11 * y1 + insc * (in + drive);
           y2 = y2n;
         }
-        if (V >= a.v_th) {
-          V = a.v_reset;
-          r = a.ref_steps;
-          const int lg = (int)(t - a.t_slice0);
-          atomicOr(&mask[lg * Wd + (n >> 5)], 1u << (n & 31));
+        if (V >= v_th) {
+          V = v_reset;
+          r = ref_steps;
+          atomicOr(&mask[(lag_upd + s) * Wd + (n >> 5)], 1u << (n & 31));
         }
         }
       }
@@ -1230,6 +1266,10 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         a.y2[gn] = y2;
       }
     }
+  };
+  if (a.n_upd > 0) {
+    if (regs) update(BoolC<true>{});
+    else update(BoolC<false>{});
   }
 
   if (a.do_deliver && !split) flush_rows(tid, kSliceThreads);
@@ -1283,6 +1323,24 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   }
 }
 
+// The slice kernels read their argument fields where they are used (kept
+// in registers for the whole kernel they would crowd out the walk's).  Each
+// first read of a 64-byte line of the argument block would then be a
+// scalar-cache miss of its own, one after another; one load per line at
+// entry, all waited for together, brings the block in with one round trip.
+template <typename T>
+__device__ __forceinline__ void touch_lines(const T* p) {
+  constexpr int kWords = (int)(sizeof(T) / 4);
+  constexpr int kLines = (kWords + 15) / 16;
+  const uint32_t* w = (const uint32_t*)p;
+  uint32_t v[kLines];
+#pragma unroll
+  for (int i = 0; i < kLines; ++i) v[i] = w[i * 16 < kWords ? i * 16 : kWords - 1];
+  // keep the loads (their values are otherwise unused)
+#pragma unroll
+  for (int i = 0; i < kLines; ++i) asm volatile("" ::"s"(v[i]));
+}
+
 // Workgroup gx serves target block map[gx].y of network map[gx].x (one
 // network, or the members of a batch), whose arguments for this slice are
 // args[map[gx].x]; map[gx].x < 0 marks a padding workgroup.  The map is
@@ -1296,6 +1354,7 @@ __global__ void __launch_bounds__(kSliceThreads)
     k_slice(const SliceArgs* __restrict__ args, const int2* __restrict__ map) {
   const int2 m = map[blockIdx.x];
   if (m.x < 0) return;
+  touch_lines(args + m.x);
   slice_block<WF, false>(args[m.x], m.y);
 }
 
@@ -1310,6 +1369,7 @@ struct SingleArgs {
 template <int WF, bool BIN>
 __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
   const SingleArgs* p = (const SingleArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  touch_lines(p);
   const int gx = blockIdx.x;
   const int b = (gx & 7) * p->per_xcd + (gx >> 3);
   if (b >= p->a.NB) return;
