@@ -472,8 +472,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
     // thread f % 1024, slot f / 1024 (consecutive lanes read consecutive
     // records of a segment).  Each thread's events of a chunk sit in
     // registers: target|delay word, weight bits, and lag / population packed
-    // four to a register.  A chunk's loads are issued while the previous
-    // chunk is written out.
+    // four to a register.  A chunk's loads are issued right after the
+    // previous chunk's write-out.
     const unsigned long long E_c = (unsigned long long)U * kBinThreads;
     constexpr int UM = W8 ? kBinMaxU8 : kBinMaxU;  // register budget
     uint32_t tdk[UM], wbr[UM], rec8[W8 ? UM : 1], m4[UM / 4];
@@ -579,8 +579,6 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
         }
       }
       __syncthreads();
-      // the next chunk's loads (the registers are free after the scatter)
-      if (f0 + E_c < n_batch) issue(f0 + E_c);
       // (5) every thread stores sorted records f, f + 1024, ...: a bin's run
       // goes to consecutive addresses (coalesced stores of ~E_c / NB
       // records), then the fills advance
@@ -617,6 +615,10 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           }
         }
       }
+      // The next chunk's loads (the registers are free after the scatter),
+      // issued after this chunk's stores: the classify's first wait for a
+      // load also waits for every store issued before it.
+      if (f0 + E_c < n_batch) issue(f0 + E_c);
       for (int b = tid; b < NB; b += kBinThreads) cc[b].y += cc[b + 1].x - cc[b].x;
       __syncthreads();
       for (int i = tid; i <= NB; i += kBinThreads) cc[i].x = 0u;
