@@ -502,12 +502,26 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
         wbr[u] = 0u;
         if (u < U && fr < n_ev) {
           const unsigned long long f = f0 + fr;
-          while (pre[sp + 1] <= f) ++sp;
-          const unsigned long long e = lo[sp] + (f - pre[sp]);
+          // the spike's bounds, segment start and meta word are read
+          // together: one LDS round trip per event, one more per row
+          // boundary crossed
+          unsigned long long p0, p1, l0;
+          uint32_t m;
+          for (;;) {
+            p0 = pre[sp];
+            p1 = pre[sp + 1];
+            l0 = lo[sp];
+            m = mt[sp];
+            // keeps the three reads in the loop (the compiler would move
+            // them after it, behind a second wait)
+            asm volatile("" : "+v"(p0), "+v"(l0), "+v"(m));
+            if (p1 > f) break;
+            ++sp;
+          }
+          const unsigned long long e = l0 + (f - p0);
           tdk[u] = a.tgtd[e];
           if constexpr (W8) wbr[u] = ((const uint32_t*)a.wbits)[e];
           else wbr[u] = ((const uint16_t*)a.wbits)[e];
-          const uint32_t m = mt[sp];
           m4[u >> 2] |= ((m & 31u) | ((m >> 10) & 32u)) << ((u & 3) * 8);  // lag | inh << 5
         }
       }
