@@ -14,7 +14,7 @@
 //   the ring in HBM by the threads without a neuron, during the update.
 //   Source-major layout: k_bin first sorts the slice's events by target
 //   block into binned records; the slice kernel then accumulates those
-//   instead of walking segments (k_slice1<form, true>).
+//   instead of walking segments (k_slice1<form, true, dyn>).
 //   k_shift_args moves the device-resident arguments of a captured batch
 //   graph on by one period.
 //
@@ -761,7 +761,8 @@ size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
 // BIN: the slice's events arrive binned by target block (source-major
 // layout, k_bin; WF_FP32 for 8-byte records, any other form for 4-byte
 // ones); otherwise they are read from the block-major segments.
-template <int WF, bool BIN>
+// DYN: how the window rows due later are flushed (see the flush below).
+template <int WF, bool BIN, bool DYN>
 __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tid = threadIdx.x;
@@ -819,9 +820,11 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // memory queues of every compute unit)
   __shared__ unsigned long long s_ev;
   __shared__ long long s_zero;  // read by the update for steps outside the window
+  __shared__ int s_fl;          // DYN: next neuron whose window rows go to the ring
   if (tid == 0) {
     s_ev = 0;
     s_zero = 0;
+    s_fl = 0;
   }
   // the list counter of a later slice starts at zero
   if (b == 0 && tid == 0 && a.zero_cnt) *a.zero_cnt = 0;
@@ -1143,7 +1146,11 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // Rows [t_first, w_lo + Dmax): all window reads first, then the stores
   // (adds into rows that already hold earlier deliveries).  Threads without
   // a neuron to update write them while the others update; when every
-  // thread updates, all write them afterwards.
+  // thread updates, all write them afterwards.  With fewer free threads
+  // than neurons (DYN, blocks of more than half a workgroup), neurons are
+  // handed out one at a time from an LDS counter and the updating threads
+  // join when their update is done; a fixed share per free thread would
+  // keep the flush running long after the update.
   auto flush_rows = [&](int t0, int stride) {
     constexpr int kFl = 8;
     const double inv = a.fx_inv;
@@ -1156,7 +1163,10 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     if (add_rows < 0) add_rows = 0;
     if (add_rows > nrows) add_rows = nrows;
     const int n_add = (int)add_rows;
-    for (int n = t0; n < nb; n += stride) {
+    for (int n = t0;; n += stride) {
+      if constexpr (DYN)
+        n = __hip_atomic_fetch_add(&s_fl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (n >= nb) break;
       for (int k0 = 0; k0 < nrows; k0 += kFl) {
         // Rows past nrows are clamped to the last one, so every read is in
         // range and none sits behind a branch: the ring loads of the rows
@@ -1288,7 +1298,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     else update(BoolC<false>{});
   }
 
-  if (a.do_deliver && !split) flush_rows(tid, kSliceThreads);
+  if (a.do_deliver && (!split || (DYN && tid < nb))) flush_rows(tid, kSliceThreads);
   __syncthreads();
 
   // ---- compaction: this block's new spikes, (lag, neuron) ordered --------
@@ -1371,7 +1381,7 @@ __global__ void __launch_bounds__(kSliceThreads)
   const int2 m = map[blockIdx.x];
   if (m.x < 0) return;
   touch_lines(args + m.x);
-  slice_block<WF, false>(args[m.x], m.y);
+  slice_block<WF, false, false>(args[m.x], m.y);
 }
 
 // One network: the arguments travel by value in the kernel-argument segment
@@ -1382,14 +1392,14 @@ struct SingleArgs {
   SliceArgs a;
   int32_t per_xcd;
 };
-template <int WF, bool BIN>
+template <int WF, bool BIN, bool DYN>
 __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
   const SingleArgs* p = (const SingleArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   touch_lines(p);
   const int gx = blockIdx.x;
   const int b = (gx & 7) * p->per_xcd + (gx >> 3);
   if (b >= p->a.NB) return;
-  slice_block<WF, BIN>(p->a, b);
+  slice_block<WF, BIN, DYN>(p->a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1550,31 +1560,38 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_ma
   return hipGetLastError();
 }
 
+template <bool DYN>
+void launch_slice1_as(hipStream_t s, const SingleArgs& sa, size_t lds, int wform) {
+  const dim3 grid((unsigned)(8 * sa.per_xcd)), block(kSliceThreads);
+  if (sa.a.bins) {
+    // binned records: 8 bytes (FP32 weight) or 4 (BF16 bits)
+    if (wform == WF_FP32) hipLaunchKernelGGL((k_slice1<WF_FP32, true, DYN>), grid, block, lds, s, sa);
+    else hipLaunchKernelGGL((k_slice1<WF_BF16, true, DYN>), grid, block, lds, s, sa);
+    return;
+  }
+  switch (wform) {
+    case WF_FP32:
+      hipLaunchKernelGGL((k_slice1<WF_FP32, false, DYN>), grid, block, lds, s, sa);
+      break;
+    case WF_BF16:
+      hipLaunchKernelGGL((k_slice1<WF_BF16, false, DYN>), grid, block, lds, s, sa);
+      break;
+    case WF_PACKED:
+      hipLaunchKernelGGL((k_slice1<WF_PACKED, false, DYN>), grid, block, lds, s, sa);
+      break;
+    default:
+      hipLaunchKernelGGL((k_slice1<WF_BF16_RESID, false, DYN>), grid, block, lds, s, sa);
+      break;
+  }
+}
+
 hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wform) {
   SingleArgs sa;
   sa.a = a;
   sa.per_xcd = (a.NB + 7) / 8;
-  const dim3 grid((unsigned)(8 * sa.per_xcd)), block(kSliceThreads);
-  if (a.bins) {
-    // binned records: 8 bytes (FP32 weight) or 4 (BF16 bits)
-    if (wform == WF_FP32) hipLaunchKernelGGL((k_slice1<WF_FP32, true>), grid, block, lds, s, sa);
-    else hipLaunchKernelGGL((k_slice1<WF_BF16, true>), grid, block, lds, s, sa);
-    return hipGetLastError();
-  }
-  switch (wform) {
-    case WF_FP32:
-      hipLaunchKernelGGL((k_slice1<WF_FP32, false>), grid, block, lds, s, sa);
-      break;
-    case WF_BF16:
-      hipLaunchKernelGGL((k_slice1<WF_BF16, false>), grid, block, lds, s, sa);
-      break;
-    case WF_PACKED:
-      hipLaunchKernelGGL((k_slice1<WF_PACKED, false>), grid, block, lds, s, sa);
-      break;
-    default:
-      hipLaunchKernelGGL((k_slice1<WF_BF16_RESID, false>), grid, block, lds, s, sa);
-      break;
-  }
+  // blocks of more than half a workgroup: fewer free threads than neurons
+  if (kSliceThreads - a.B < a.B) launch_slice1_as<true>(s, sa, lds, wform);
+  else launch_slice1_as<false>(s, sa, lds, wform);
   return hipGetLastError();
 }
 
