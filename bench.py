@@ -299,12 +299,54 @@ def cpu_baseline(cfg: dict, budget_s: float = 12.0, frac: int = 16) -> dict:
                       f"{dt:.1f} s"}
 
 
+def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
+    """The paper's own delivery algorithms on the host (Alg. REF, Sec. 3.2;
+    Alg. bwTSRB* with B_TS = B_RB = 16, Sec. 4.4): each thread owns a share
+    of the 112,500 targets with its own source-indexed table (Sec. 3.1), all
+    of the 1.27e9-synapse network in FP64, drawn on the host.  Delivery only,
+    of the GPU run's ~900 spikes per 1 ms slice; the same seeded lists for
+    both algorithms."""
+    from paper_2109_12855_amd import sdcpu, workloads
+
+    base = workloads.ALPHA_112K
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    n = base["n_exc"] + base["n_inh"]
+    t0 = time.time()
+    net = sdcpu.CpuNet.generate(n_tgt=n, n_src_exc=base["n_exc"], n_src_inh=base["n_inh"],
+                                k_exc=base["k_exc"], k_inh=base["k_inh"], d_lo=base["d_lo"],
+                                d_hi=base["d_hi"], w_exc=base["w_exc"], g=base["g"],
+                                seed=base["seed"], ring_len=base["ring_len"], n_threads=threads)
+    build_s = time.time() - t0
+    d_min = base["d_min"]
+    spikes = int(round(n * 8.0 * d_min * base["h"] * 1e-3))
+    lists = [workloads.replay_spikes(n, spikes, d_min, seed=5000 + k) for k in range(slices + 2)]
+    out = {"workload": "alpha_112500 tables on the host (1.27e9 synapses, FP64 weights), "
+                       "delivery only",
+           "threads": net.n_threads, "synapses": net.n_synapses, "build_s": round(build_s, 1),
+           "spikes_per_slice": spikes, "slices": slices, "b_ts": 16, "b_rb": 16}
+    for name, alg in (("ref", sdcpu.REF), ("bwtsrb", sdcpu.BWTSRB)):
+        net.clear()
+        for k in range(2):  # warm-up
+            net.deliver(*lists[k], k * d_min, alg=alg)
+        ev = 0
+        t = time.perf_counter()
+        for k in range(slices):
+            ev += net.deliver(*lists[k + 2], (k + 2) * d_min, alg=alg)
+        dt = time.perf_counter() - t
+        out[name] = {"events_per_s": ev / dt, "ms_per_slice": dt / slices * 1e3}
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000, help="timed slices (1 ms each)")
     ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu-paper", action="store_true",
+                    help="skip the multithreaded CPU REF / bwTSRB* comparator")
     ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
     ap.add_argument("--no-brain-share", action="store_true",
                     help="skip the 1.27e10-synapse brain-scale share measurement")
@@ -362,6 +404,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(dict(base, wform=0))
+    cpu_paper = None
+    if not args.no_cpu_paper:
+        cpu_paper = cpu_paper_algorithms()
+        _log("cpu paper algorithms: " + json.dumps(cpu_paper))
     roof = None
     if "kernel_ms" in head:
         tr = measured_traffic() if head_name == "bf16_packed" else None
@@ -394,6 +440,7 @@ def main():
         "sweep": sw,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_paper_algorithms": cpu_paper,
     }
     print(json.dumps(line), flush=True)
 

@@ -8,6 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdeliver.so")
+CPU_LIB = os.path.join(HERE, "libsdcpu.so")
+CPU_SOURCES = [os.path.join(HERE, "cpu", "sd_cpu.c")]
 SOURCES = [os.path.join(CSRC, "sd_api.cpp"), os.path.join(CSRC, "sd_autotune.cpp"),
            os.path.join(CSRC, "sd_kernels.hip")]
 ARCH = os.environ.get("SD_OFFLOAD_ARCH", "gfx950")
@@ -33,7 +35,20 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
+    build_cpu()
     return LIB
+
+
+def build_cpu() -> str:
+    """Compile the multithreaded CPU delivery comparator into libsdcpu.so."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-o", tmp,
+           *CPU_SOURCES]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
 
 
 if __name__ == "__main__":
