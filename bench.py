@@ -325,16 +325,22 @@ def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
                        "delivery only",
            "threads": net.n_threads, "synapses": net.n_synapses, "build_s": round(build_s, 1),
            "spikes_per_slice": spikes, "slices": slices, "b_ts": 16, "b_rb": 16}
-    for name, alg in (("ref", sdcpu.REF), ("bwtsrb", sdcpu.BWTSRB)):
-        net.clear()
-        for k in range(2):  # warm-up
-            net.deliver(*lists[k], k * d_min, alg=alg)
-        ev = 0
-        t = time.perf_counter()
-        for k in range(slices):
-            ev += net.deliver(*lists[k + 2], (k + 2) * d_min, alg=alg)
-        dt = time.perf_counter() - t
-        out[name] = {"events_per_s": ev / dt, "ms_per_slice": dt / slices * 1e3}
+    # ring buffers packed back to back (this build's layout), then inside
+    # 1 KB neuron objects (stride 128 cells), as in the simulator the paper
+    # studies, where the ring-buffer accesses miss the caches
+    for layout, stride in (("packed", base["ring_len"]), ("objects_1kb", 128)):
+        net.set_ring_stride(stride)
+        for name, alg in (("ref", sdcpu.REF), ("bwtsrb", sdcpu.BWTSRB)):
+            net.clear()
+            for k in range(2):  # warm-up
+                net.deliver(*lists[k], k * d_min, alg=alg)
+            ev = 0
+            t = time.perf_counter()
+            for k in range(slices):
+                ev += net.deliver(*lists[k + 2], (k + 2) * d_min, alg=alg)
+            dt = time.perf_counter() - t
+            key = name if layout == "packed" else f"{name}_{layout}"
+            out[key] = {"events_per_s": ev / dt, "ms_per_slice": dt / slices * 1e3}
     net.close()
     return out
 

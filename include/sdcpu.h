@@ -59,6 +59,12 @@ int64_t sdc_deliver(sdc_net* net, const uint32_t* src, const uint8_t* lag, int64
 int sdc_read_ring(const sdc_net* net, double* out);
 /* Zero every ring buffer. */
 void sdc_clear(sdc_net* net);
+/* Place neuron j's ring buffer at cell j * stride of its thread's array
+ * (stride >= ring_len; ring_len by default, the rings packed back to back).
+ * A larger stride stands for ring buffers held inside larger neuron objects,
+ * as in the simulator the paper studies: fewer of them share a cache line
+ * or fit in the caches.  The rings are reallocated and zeroed. */
+int sdc_set_ring_stride(sdc_net* net, int32_t stride);
 int64_t sdc_n_synapses(const sdc_net* net);
 int32_t sdc_n_threads(const sdc_net* net);
 void sdc_destroy(sdc_net* net);

@@ -19,12 +19,13 @@ typedef struct {
   uint32_t* tgt;   /* local target index */
   uint8_t* dly;
   double* w;
-  double* rb;      /* [hi - lo][ring_len] */
+  double* rb;      /* [hi - lo][stride], ring_len cells used per neuron */
 } part;
 
 struct sdc_net {
   int64_t n_src, n_tgt, n_syn;
   int32_t L, T;
+  int32_t stride;  /* cells between two neurons' ring buffers (>= L) */
   part* p;
 };
 
@@ -52,6 +53,7 @@ static sdc_net* new_net(int64_t n_src, int64_t n_tgt, int32_t L, int32_t T) {
   n->n_tgt = n_tgt;
   n->L = L;
   n->T = T;
+  n->stride = L;
   n->p = (part*)calloc((size_t)T, sizeof(part));
   if (!n->p) {
     free(n);
@@ -69,7 +71,7 @@ static int alloc_part(part* q, int64_t n_src, int64_t m, int32_t L) {
   q->tgt = (uint32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
   q->dly = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
   q->w = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
-  q->rb = (double*)calloc((size_t)(q->hi - q->lo) * (size_t)L, sizeof(double));
+  q->rb = (double*)calloc((size_t)(q->hi - q->lo) * (size_t)L, sizeof(double));  /* stride L */
   return (q->row && q->tgt && q->dly && q->w && q->rb) ? 0 : -1;
 }
 
@@ -270,7 +272,7 @@ typedef struct {
 
 /* Alg. REF: every spike entry in list order, its target segment synapse by
  * synapse, each weight added into the target's ring buffer at once. */
-static int64_t deliver_ref(part* q, int32_t L, const del_job* j) {
+static int64_t deliver_ref(part* q, int32_t L, int64_t S, const del_job* j) {
   int64_t ev = 0;
   for (int64_t i = 0; i < j->n_spk; ++i) {
     const uint32_t s = j->src[i];
@@ -278,7 +280,7 @@ static int64_t deliver_ref(part* q, int32_t L, const del_job* j) {
     for (int64_t e = q->row[s]; e < q->row[s + 1]; ++e) {
       int slot = base + q->dly[e];
       if (slot >= L) slot -= L;
-      q->rb[(int64_t)q->tgt[e] * L + slot] += q->w[e];
+      q->rb[(int64_t)q->tgt[e] * S + slot] += q->w[e];
     }
     ev += q->row[s + 1] - q->row[s];
   }
@@ -289,7 +291,7 @@ static int64_t deliver_ref(part* q, int32_t L, const del_job* j) {
  * sizes read first), the synapses of a batch's segments staged as (ring
  * buffer cell, weight) in batches of b_rb across segment boundaries; a full
  * batch is prefetched as a group, then its weights are added in order. */
-static int64_t deliver_bwtsrb(part* q, int32_t L, const del_job* j) {
+static int64_t deliver_bwtsrb(part* q, int32_t L, int64_t S, const del_job* j) {
   int64_t lcid[SDC_MAX_BATCH], ts_size[SDC_MAX_BATCH];
   int base[SDC_MAX_BATCH];
   double* cell[SDC_MAX_BATCH];
@@ -310,7 +312,7 @@ static int64_t deliver_bwtsrb(part* q, int32_t L, const del_job* j) {
         const int64_t e = lcid[k]++;
         int slot = base[k] + q->dly[e];
         if (slot >= L) slot -= L;
-        cell[i] = &q->rb[(int64_t)q->tgt[e] * L + slot];
+        cell[i] = &q->rb[(int64_t)q->tgt[e] * S + slot];
         wv[i] = q->w[e];
         if (++i == B_RB) {
           for (int r = 0; r < B_RB; ++r) __builtin_prefetch(cell[r], 1, 3);
@@ -328,7 +330,9 @@ static int64_t deliver_bwtsrb(part* q, int32_t L, const del_job* j) {
 static void* del_worker(void* arg) {
   del_job* j = (del_job*)arg;
   part* q = &j->n->p[j->t];
-  j->events = j->alg == SDC_REF ? deliver_ref(q, j->n->L, j) : deliver_bwtsrb(q, j->n->L, j);
+  const sdc_net* n = j->n;
+  j->events = j->alg == SDC_REF ? deliver_ref(q, n->L, n->stride, j)
+                                 : deliver_bwtsrb(q, n->L, n->stride, j);
   return NULL;
 }
 
@@ -360,7 +364,8 @@ int sdc_read_ring(const sdc_net* n, double* out) {
   for (int t = 0; t < n->T; ++t) {
     const part* q = &n->p[t];
     for (int64_t j = q->lo; j < q->hi; ++j)
-      for (int32_t s = 0; s < n->L; ++s) out[(int64_t)s * n->n_tgt + j] = q->rb[(j - q->lo) * n->L + s];
+      for (int32_t s = 0; s < n->L; ++s)
+        out[(int64_t)s * n->n_tgt + j] = q->rb[(j - q->lo) * n->stride + s];
   }
   return 0;
 }
@@ -368,7 +373,28 @@ int sdc_read_ring(const sdc_net* n, double* out) {
 void sdc_clear(sdc_net* n) {
   if (!n) return;
   for (int t = 0; t < n->T; ++t)
-    memset(n->p[t].rb, 0, (size_t)(n->p[t].hi - n->p[t].lo) * (size_t)n->L * sizeof(double));
+    memset(n->p[t].rb, 0, (size_t)(n->p[t].hi - n->p[t].lo) * (size_t)n->stride * sizeof(double));
+}
+
+int sdc_set_ring_stride(sdc_net* n, int32_t stride) {
+  if (!n || stride < n->L) return -1;
+  double** fresh = (double**)calloc((size_t)n->T, sizeof(double*));
+  if (!fresh) return -1;
+  for (int t = 0; t < n->T; ++t) {
+    fresh[t] = (double*)calloc((size_t)(n->p[t].hi - n->p[t].lo) * (size_t)stride, sizeof(double));
+    if (!fresh[t]) {
+      for (int u = 0; u <= t; ++u) free(fresh[u]);
+      free(fresh);
+      return -1;
+    }
+  }
+  for (int t = 0; t < n->T; ++t) {
+    free(n->p[t].rb);
+    n->p[t].rb = fresh[t];
+  }
+  free(fresh);
+  n->stride = stride;
+  return 0;
 }
 
 int64_t sdc_n_synapses(const sdc_net* n) { return n ? n->n_syn : -1; }

@@ -30,6 +30,8 @@ def lib():
         L.sdc_read_ring.argtypes = [vp, vp]
         L.sdc_read_ring.restype = C.c_int
         L.sdc_clear.argtypes = [vp]
+        L.sdc_set_ring_stride.argtypes = [vp, i32]
+        L.sdc_set_ring_stride.restype = C.c_int
         L.sdc_n_synapses.argtypes = [vp]
         L.sdc_n_synapses.restype = i64
         L.sdc_n_threads.argtypes = [vp]
@@ -87,6 +89,11 @@ class CpuNet:
 
     def clear(self):
         lib().sdc_clear(self._h)
+
+    def set_ring_stride(self, stride: int):
+        """Ring buffers inside neuron objects of `stride` cells (zeroes them)."""
+        if lib().sdc_set_ring_stride(self._h, int(stride)) != 0:
+            raise ValueError("sdc_set_ring_stride: stride below ring_len or out of memory")
 
     @property
     def n_synapses(self) -> int:

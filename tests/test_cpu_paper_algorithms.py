@@ -24,7 +24,8 @@ def _oracle_case(seed=11, n=700, k=120, d_lo=2, d_hi=9):
 
 @pytest.mark.parametrize("threads", [1, 2, 5])
 @pytest.mark.parametrize("b_ts,b_rb", [(16, 16), (1, 1), (3, 7), (64, 5)])
-def test_bwtsrb_equals_ref_and_oracle_bitwise(threads, b_ts, b_rb):
+@pytest.mark.parametrize("stride", [0, 45])
+def test_bwtsrb_equals_ref_and_oracle_bitwise(threads, b_ts, b_rb, stride):
     cfg, ref, (row, tgt, dly, w) = _oracle_case()
     n = cfg["n_exc"] + cfg["n_inh"]
     src, lag = W.replay_spikes(n, 300, cfg["d_min"], seed=4)
@@ -34,6 +35,8 @@ def test_bwtsrb_equals_ref_and_oracle_bitwise(threads, b_ts, b_rb):
     for alg in (sdcpu.REF, sdcpu.BWTSRB):
         net = sdcpu.CpuNet.from_csr(row, tgt, dly, w, n, cfg["ring_len"], threads)
         assert net.n_threads == threads
+        if stride:  # ring buffers inside larger neuron objects
+            net.set_ring_stride(stride)
         ev = net.deliver(src, lag, t0, alg=alg, b_ts=b_ts, b_rb=b_rb)
         assert ev == ne
         rings.append(net.ring())
@@ -84,6 +87,8 @@ def test_empty_list_and_invalid_arguments():
         net.deliver(np.array([0], np.uint32), np.zeros(1, np.uint8), 0, alg=sdcpu.BWTSRB, b_ts=0)
     with pytest.raises(ValueError):
         net.deliver(np.array([0], np.uint32), np.zeros(1, np.uint8), 0, alg=7)
+    with pytest.raises(ValueError):
+        net.set_ring_stride(cfg["ring_len"] - 1)  # rings would overlap
     bad = dly.copy()
     bad[0] = cfg["ring_len"]  # delay does not fit the ring
     with pytest.raises(ValueError):
