@@ -32,7 +32,9 @@ enum { SDC_REF = 0, SDC_BWTSRB = 1 };
 /* Tables from a source-major CSR over all targets (Sec. 3.1): row[n_src+1]
  * (int64 offsets), tgt[e] in [0, n_tgt), dly[e] in [1, ring_len), w[e].
  * Targets are split into n_threads contiguous ranges; each thread keeps the
- * synapses of its targets in the input order.  The arrays are copied. */
+ * synapses of its targets in the input order.  The arrays are copied.
+ * Returns NULL for offsets that do not start at 0 or decrease, targets or
+ * delays out of range, or out of memory. */
 sdc_net* sdc_create_from_csr(int64_t n_src, int64_t n_tgt, const int64_t* row,
                              const int32_t* tgt, const uint8_t* dly, const double* w,
                              int32_t ring_len, int32_t n_threads);

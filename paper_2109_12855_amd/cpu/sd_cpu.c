@@ -133,6 +133,9 @@ sdc_net* sdc_create_from_csr(int64_t n_src, int64_t n_tgt, const int64_t* row,
                              const int32_t* tgt, const uint8_t* dly, const double* w,
                              int32_t ring_len, int32_t n_threads) {
   if (!row || !tgt || !dly || !w) return NULL;
+  if (n_src < 1 || row[0] != 0) return NULL;
+  for (int64_t s = 0; s < n_src; ++s)
+    if (row[s + 1] < row[s]) return NULL;  /* offsets must not decrease */
   sdc_net* n = new_net(n_src, n_tgt, ring_len, n_threads);
   if (!n) return NULL;
   for (int64_t e = 0; e < row[n_src]; ++e)

@@ -93,6 +93,14 @@ def test_empty_list_and_invalid_arguments():
     bad[0] = cfg["ring_len"]  # delay does not fit the ring
     with pytest.raises(ValueError):
         sdcpu.CpuNet.from_csr(row, tgt, bad, w, n, cfg["ring_len"], 2)
+    bad_row = row.copy()
+    bad_row[3], bad_row[4] = bad_row[4], bad_row[3] - 1  # decreasing offsets
+    with pytest.raises(ValueError):
+        sdcpu.CpuNet.from_csr(bad_row, tgt, dly, w, n, cfg["ring_len"], 2)
+    bad_tgt = tgt.copy()
+    bad_tgt[-1] = n  # target out of range
+    with pytest.raises(ValueError):
+        sdcpu.CpuNet.from_csr(row, bad_tgt, dly, w, n, cfg["ring_len"], 2)
 
 
 def test_generated_network_thread_invariant():
