@@ -296,7 +296,9 @@ int64_t sd_batch_graph_launches(const sd_batch* b);
  * Block sizes for n networks (n = 1: one context; n > 1: a batch, whose
  * members must be block-major).  For each target T in targets[0..n_targets)
  * member i gets block_neurons = ceil(N_i / T) rounded up to 64, lowered in
- * steps of 64 until its layout fits; each candidate is created, built and
+ * steps of 64 until its layout fits; a batch also gets a balanced candidate
+ * per T, member i split into round(T * K_i / mean K) blocks (the events per
+ * block grow with the in-degree K).  Each candidate is created, built and
  * timed over `slices` slices after `warmup` slices on a private stream of
  * the current device, and the fastest candidate's sizes go to
  * h_block_neurons[0..n), its time per slice (us) to *us_per_slice (may be

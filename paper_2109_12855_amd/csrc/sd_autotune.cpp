@@ -7,6 +7,11 @@
 // workgroups but walk short segments, large blocks walk long segments with
 // fewer workgroups and fewer resident per compute unit.  Which side wins
 // depends on the network sizes and rates, so it is measured.
+//
+// For a batch two rules give a candidate per target T: every member split
+// into T blocks (uniform), or member i into T * K_i / mean(K) blocks
+// (balanced: the events per block of a slice grow with the in-degree, and
+// one launch waits for its slowest blocks).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,6 +48,8 @@ uint64_t problem_hash(const sd_config* cfgs, int32_t n, const int32_t* targets, 
 #undef SD_MIX
   }
   h = fnv(h, targets, sizeof(int32_t) * (size_t)nt);
+  const uint32_t rules = 2;  // uniform and balanced candidates
+  h = fnv(h, &rules, sizeof rules);
   h = fnv(h, &warmup, sizeof warmup);
   h = fnv(h, &slices, sizeof slices);
   return h;
@@ -98,16 +105,17 @@ bool cache_lookup(const std::string& text, const std::string& key, int32_t n,
   return (int32_t)bn->size() == n;
 }
 
-bool cache_store(const char* path, const std::string& key, int32_t target, double us,
-                 const std::vector<int32_t>& bn) {
+bool cache_store(const char* path, const std::string& key, int32_t target, const char* rule,
+                 double us, const std::vector<int32_t>& bn) {
   std::string text = read_file(path);
   const size_t close = text.rfind('}');
   if (text.find('{') == std::string::npos || close == std::string::npos) text = "{\n}\n";
   const size_t last = text.rfind('}');
   const bool empty = text.find('"') == std::string::npos;
   char head[256];
-  std::snprintf(head, sizeof head, "  \"%s\": {\"target\": %d, \"us_per_slice\": %.3f, ",
-                key.c_str(), target, us);
+  std::snprintf(head, sizeof head,
+                "  \"%s\": {\"target\": %d, \"rule\": \"%s\", \"us_per_slice\": %.3f, ",
+                key.c_str(), target, rule, us);
   std::string entry = std::string(empty ? "" : ",\n") + head + "\"block_neurons\": [";
   for (size_t i = 0; i < bn.size(); ++i) entry += (i ? ", " : "") + std::to_string(bn[i]);
   entry += "]}\n";
@@ -121,12 +129,13 @@ bool cache_store(const char* path, const std::string& key, int32_t target, doubl
   return std::fclose(f) == 0 && ok;
 }
 
-// Block size of a network for a target of T blocks: ceil(N / T) rounded up
-// to 64, lowered in steps of 64 until the layout fits (block-major for a
-// batch member).
-int32_t block_for(const sd_config& c, int32_t T, bool batch) {
+// Block size of a network for a target of T blocks scaled by s (rounded, at
+// least one block): ceil(N / blocks) rounded up to 64, lowered in steps of
+// 64 until the layout fits (block-major for a batch member).
+int32_t block_for(const sd_config& c, int32_t T, double s, bool batch) {
   const int64_t N = c.n_exc + c.n_inh;
-  int64_t b = (N + T - 1) / T;
+  const int64_t nb = std::max<int64_t>(1, std::llround((double)T * s));
+  int64_t b = (N + nb - 1) / nb;
   b = std::max<int64_t>(64, (b + 63) / 64 * 64);
   b = std::min<int64_t>(b, 1 << 16);
   for (; b >= 64; b -= 64) {
@@ -202,29 +211,38 @@ sd_status sd_autotune(const sd_config* cfgs, int32_t n, const int32_t* targets, 
     return SD_OK;
   }
   const bool batch = n > 1;
+  double k_mean = 0.0;
+  for (int32_t i = 0; i < n; ++i) k_mean += (double)(cfgs[i].k_exc + cfgs[i].k_inh);
+  k_mean = std::max(k_mean / n, 1.0);
   int32_t best_t = 0;
+  const char* best_rule = "uniform";
   for (int32_t k = 0; k < n_targets; ++k) {
-    std::vector<sd_config> cand(cfgs, cfgs + n);
-    std::vector<int32_t> bn((size_t)n);
-    bool ok = true;
-    for (int32_t i = 0; i < n && ok; ++i) {
-      bn[(size_t)i] = block_for(cfgs[i], targets[k], batch);
-      ok = bn[(size_t)i] > 0;
-      cand[(size_t)i].block_neurons = bn[(size_t)i];
-      cand[(size_t)i].record_spikes = 0;
-    }
-    if (!ok) continue;
-    const double us = time_candidate(cand, warmup, slices);
-    if (us > 0.0 && (best_us < 0.0 || us < best_us)) {
-      best_us = us;
-      best = bn;
-      best_t = targets[k];
+    for (int rule = 0; rule < (batch ? 2 : 1); ++rule) {
+      std::vector<sd_config> cand(cfgs, cfgs + n);
+      std::vector<int32_t> bn((size_t)n);
+      bool ok = true;
+      for (int32_t i = 0; i < n && ok; ++i) {
+        const double s = rule ? (double)(cfgs[i].k_exc + cfgs[i].k_inh) / k_mean : 1.0;
+        bn[(size_t)i] = block_for(cfgs[i], targets[k], s, batch);
+        ok = bn[(size_t)i] > 0;
+        cand[(size_t)i].block_neurons = bn[(size_t)i];
+        cand[(size_t)i].record_spikes = 0;
+      }
+      if (!ok) continue;
+      const double us = time_candidate(cand, warmup, slices);
+      if (us > 0.0 && (best_us < 0.0 || us < best_us)) {
+        best_us = us;
+        best = bn;
+        best_t = targets[k];
+        best_rule = rule ? "balanced" : "uniform";
+      }
     }
   }
   if (best_us < 0.0) return SD_EUNSUPPORTED;
   std::copy(best.begin(), best.end(), h_block_neurons);
   if (us_per_slice) *us_per_slice = best_us;
-  if (cache_path && !cache_store(cache_path, key, best_t, best_us, best)) return SD_EINVAL;
+  if (cache_path && !cache_store(cache_path, key, best_t, best_rule, best_us, best))
+    return SD_EINVAL;
   return SD_OK;
 }
 
