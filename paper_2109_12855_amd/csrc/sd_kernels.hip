@@ -532,28 +532,44 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
       // classify: tdk[u] becomes the event's key (block << 16 | rank in the
       // block's bin), wbr[u] (4-byte form) or rec8[u] (FP32) its record
+      // Eight events at a time: their rank atomics are all issued before
+      // the first rank is used, so one wait covers them.  The block size
+      // and its inverse are copied to vector registers first: read from the
+      // scalar registers a scalar load filled, each event would wait on the
+      // counter that the previous event's LDS atomic also counts against.
+      float inv_B = a.inv_B;
+      int Bv = B;
+      asm volatile("" : "+v"(inv_B), "+v"(Bv));
 #pragma unroll
-      for (int u = 0; u < UM; ++u) {
-        const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
-        const uint32_t td = tdk[u];
-        tdk[u] = 0xffffffffu;  // no event
-        if constexpr (W8) rec8[u] = 0u;
-        if (u < U && fr < n_ev) {
-          const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 63u;
-          const int tgt = (int)(td & tmask);
-          // block = tgt / B from an FP32 estimate, corrected by one step
-          int blk = (int)((float)tgt * a.inv_B);
-          int off = tgt - blk * B;
-          if (off < 0) { --blk; off += B; }
-          if (off >= B) { ++blk; off -= B; }
-          const int q = (int)(m & 31u) + (int)(td >> kTgtBits);
-          const uint32_t r = (uint32_t)(q * B + off) | ((m & 32u) << 10);
-          if constexpr (W8) rec8[u] = r;
-          else wbr[u] = r | (wbr[u] << 16);
-          const uint32_t rank = __hip_atomic_fetch_add(&cc[blk].x, 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-          tdk[u] = ((uint32_t)blk << 16) | rank;
+      for (int h = 0; h < UM; h += 8) {
+        uint32_t rk[8];
+#pragma unroll
+        for (int u = h; u < h + 8 && u < UM; ++u) {
+          const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+          const uint32_t td = tdk[u];
+          tdk[u] = 0xffffffffu;  // no event
+          rk[u - h] = 0u;
+          if constexpr (W8) rec8[u] = 0u;
+          if (u < U && fr < n_ev) {
+            const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 63u;
+            const int tgt = (int)(td & tmask);
+            // block = tgt / B from an FP32 estimate, corrected by one step
+            int blk = (int)((float)tgt * inv_B);
+            int off = tgt - blk * Bv;
+            if (off < 0) { --blk; off += Bv; }
+            if (off >= Bv) { ++blk; off -= Bv; }
+            const int q = (int)(m & 31u) + (int)(td >> kTgtBits);
+            const uint32_t r = (uint32_t)(q * Bv + off) | ((m & 32u) << 10);
+            if constexpr (W8) rec8[u] = r;
+            else wbr[u] = r | (wbr[u] << 16);
+            rk[u - h] = __hip_atomic_fetch_add(&cc[blk].x, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            tdk[u] = (uint32_t)blk << 16;
+          }
         }
+#pragma unroll
+        for (int u = h; u < h + 8 && u < UM; ++u)
+          if (tdk[u] != 0xffffffffu) tdk[u] |= rk[u - h];
       }
       __syncthreads();
       // (3) bin starts: exclusive scan of the counts, in place
