@@ -188,3 +188,37 @@ def pending_ring(res: dict, cfg: dict, t_now: int, t_delivered: int, n_slots: in
                 rb[i] += W[d] @ S[t_sp]
                 cnt[i] += Cn[d] @ S[t_sp].astype(np.int64)
     return rb, cnt
+
+
+STREAM_SRC = 4
+
+
+def open_loop_spikes(cfg: dict, t0: int, n_steps: int):
+    """Open-loop virtual sources, drawn independently of the C oracle.
+
+    Source s fires at step t when the 32-bit uniform of step t (the low half
+    of word (t mod 8) // 2 of the Philox block at counter (s, t // 8) for even
+    t, the high half for odd t) lies below floor(2^32 p), with
+    p = 1 - exp(-rate h) the Bernoulli probability of one step.  Returns
+    (src, lag) in (lag, src) order, lag = t - t0.  numpy supplies every
+    Philox block; each block is drawn once and its eight halves reused."""
+    n_src = cfg["n_src_exc"] + cfg["n_src_inh"]
+    p = -math.expm1(-cfg["src_rate_hz"] * cfg["h"] * 1e-3)
+    thr = math.floor(p * 2.0**32)
+    c_lo, c_hi = t0 >> 3, (t0 + n_steps - 1) >> 3
+    # halves[s, c - c_lo, q]: uniform of step 8 c + q
+    halves = np.zeros((n_src, c_hi - c_lo + 1, 8), np.uint64)
+    for s in range(n_src):
+        for c in range(c_lo, c_hi + 1):
+            words = philox_words(cfg["seed"], STREAM_SRC, s, c)
+            for q in range(8):
+                w = words[q >> 1]
+                halves[s, c - c_lo, q] = (w >> 32) if (q & 1) else (w & 0xFFFFFFFF)
+    src, lag = [], []
+    for l in range(n_steps):
+        t = t0 + l
+        u = halves[:, (t >> 3) - c_lo, t & 7]
+        for s in np.flatnonzero(u < thr):
+            src.append(int(s))
+            lag.append(l)
+    return np.array(src, np.uint32), np.array(lag, np.uint8)
