@@ -141,7 +141,9 @@ typedef struct {
   int64_t spikes_delivered;  /* spike entries delivered                          */
   int64_t slices;            /* fused slice launches                            */
   int64_t spikes_recorded;   /* entries in the raster                           */
-  int32_t overflow;          /* sticky device overflow flags                    */
+  int32_t overflow;          /* sticky device flags: bit 0 spike-list overflow,  */
+                             /* bit 1 raster overflow, bits 2-3 invalid entries  */
+                             /* of an external spike list (SD_EINVAL)            */
 } sd_stats;
 
 /* Sizes the context needs for this configuration (no device work). */
@@ -175,11 +177,17 @@ sd_status sd_build_connections(sd_ctx* ctx);
  * integers, so the order does not change results). */
 sd_status sd_update_neurons(sd_ctx* ctx, int32_t n_steps);
 
-/* Deliver spikes (Alg. REF result): for every spike (src, lag) and every
- * synapse (src -> j, delay d, weight w): ring[t0 + lag + d][j] += w.
- * d_src/d_lag: n device entries (n == 0: nothing to add), lag in [0, d_min),
- * src < n_src.  The window [t0 + d_min, t0 + d_min + d_max) of possible
- * arrival steps must lie in [t_now, t_now + ring_len); otherwise SD_EINVAL. */
+/* Deliver spikes (Alg. REF result, Sec. 3.2): for every spike (src, lag) and
+ * every synapse (src -> j, delay d, weight w): ring[t0 + lag + d][j] += w.
+ * d_src/d_lag: n device entries (u32 source ids, u8 lags), borrowed until the
+ * stream reaches the call; n == 0: nothing to add.  0 <= n <= n_blocks *
+ * block_neurons * d_min (the context's list capacity), else SD_EINVAL.  The list is packed
+ * and validated on the device into the context's own buffer (no host round
+ * trip, no allocation): an entry with src >= n_src or lag >= d_min delivers
+ * nothing and sets a sticky flag that the next sd_get_stats reports as
+ * SD_EINVAL (bit 3 of sd_stats.overflow).  The window [t0 + d_min,
+ * t0 + d_min + d_max) of possible arrival steps must lie in
+ * [t_now, t_now + ring_len); otherwise SD_EINVAL at the call. */
 sd_status sd_deliver_spikes(sd_ctx* ctx, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
                             int64_t t0);
 /* Deliver the context's own completed slice (its spikes emitted in the last

@@ -11,7 +11,6 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sdeliver.h"
 #include "sd_internal.h"
 
 using namespace sd;
@@ -251,6 +250,8 @@ struct sd_ctx {
   int32_t* r = nullptr;
   float* rb = nullptr;
   uint32_t* list[2] = {nullptr, nullptr};
+  uint32_t* ext_list = nullptr;  // packed external spike list (list_cap entries)
+  int32_t* ext_cnt = nullptr;    // its entry count (device)
   // list counters rotate over three words: the open slice's (ci), the next
   // one (always zero between calls) and the one before (cleared by the next
   // fused launch)
@@ -385,7 +386,8 @@ struct Layout {
   int32_t bin_P = 0, bin_cap = 0, bin_U = 0;  // binning (source-major)
   size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
-      off_counters, off_overflow, off_bins, off_bcnt, off_spill, off_sflag, total;
+      off_counters, off_overflow, off_bins, off_bcnt, off_spill, off_sflag, off_ext, off_extcnt,
+      total;
 };
 
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS of one gfx950 workgroup
@@ -543,6 +545,9 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_bcnt = take(L->sm ? (size_t)L->NB * L->bin_P * 4 : 0);
   L->off_spill = take(L->sm ? (size_t)c->d_max * L->N * 8 : 0);
   L->off_sflag = take(L->sm ? (size_t)L->NB * 4 : 0);
+  // external spike lists (sd_deliver_spikes): packed entries and their count
+  L->off_ext = take((size_t)L->list_cap * 4);
+  L->off_extcnt = take(4);
   L->total = o;
   sd_sizes& z = L->sz;
   z.n_local = L->N;
@@ -604,7 +609,7 @@ SliceArgs base_args(sd_ctx* c) {
       a.wm1_e = a.wm1_i = sc;
     }
   }
-  a.fx_inv = std::ldexp(1.0, -c->fx_shift);
+  a.fx_inv = std::ldexp(1.0f, -c->fx_shift);
   a.grid_per_xcd = c->grid_per_xcd;
   a.V = c->V;
   a.y1 = c->y1;
@@ -821,6 +826,8 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->rb = (float*)(A + L.off_rb);
   c->list[0] = (uint32_t*)(A + L.off_list0);
   c->list[1] = (uint32_t*)(A + L.off_list1);
+  c->ext_list = (uint32_t*)(A + L.off_ext);
+  c->ext_cnt = (int32_t*)(A + L.off_extcnt);
   c->cnt3 = (int32_t*)(A + L.off_cnt);
   c->rec = (uint2*)(A + L.off_rec);
   c->wtab_e = A + L.off_wte;
@@ -1052,32 +1059,47 @@ sd_status sd_update_neurons(sd_ctx* c, int32_t n_steps) {
 
 namespace {
 sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t* d_lag,
-                       int64_t n, int64_t t0);
+                       int64_t n, int64_t t0, uint32_t* list, int32_t* list_cnt, int64_t cap);
 }
 
 sd_status sd_deliver_spikes(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
                             int64_t t0) {
   if (!c) return SD_EINVAL;
   if (n < 0 || (n > 0 && (!d_src || !d_lag))) return fail(c, SD_EINVAL, "bad spike list");
-  return deliver_impl(c, false, d_src, d_lag, n, t0);
+  return deliver_impl(c, false, d_src, d_lag, n, t0, c->ext_list, c->ext_cnt, c->list_cap);
 }
 
 sd_status sd_deliver_pending(sd_ctx* c) {
   if (!c) return SD_EINVAL;
-  return deliver_impl(c, true, nullptr, nullptr, 0, 0);
+  return deliver_impl(c, true, nullptr, nullptr, 0, 0, nullptr, nullptr, 0);
 }
+
+}  // extern "C"
+
+namespace sd {
+// sd_deliver_spikes with the packed list and its count in caller-chosen
+// device memory of cap entries (the no-allocation entry point's scratch).
+sd_status deliver_external(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
+                           int64_t t0, uint32_t* list, int32_t* list_cnt, int64_t cap) {
+  if (!c) return SD_EINVAL;
+  if (n < 0 || (n > 0 && (!d_src || !d_lag))) return fail(c, SD_EINVAL, "bad spike list");
+  return deliver_impl(c, false, d_src, d_lag, n, t0, list, list_cnt, std::min(cap, c->list_cap));
+}
+sd_status set_error(sd_ctx* c, sd_status st, const char* msg) { return fail(c, st, "%s", msg); }
+int ctx_device(const sd_ctx* c) { return c->device; }
+}  // namespace sd
+
+extern "C" {
 
 namespace {
 sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t* d_lag,
-                       int64_t n, int64_t t0) {
+                       int64_t n, int64_t t0, uint32_t* list, int32_t* list_cnt, int64_t cap) {
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   const sd_config& g = c->cfg;
   SliceArgs a = base_args(c);
   a.do_deliver = 1;
   a.n_upd = 0;
   a.t_upd = c->t_now;
-  uint32_t* packed = nullptr;
-  int32_t* d_n = nullptr;
   if (own) {
     if (!c->pend_open || c->t_now % g.d_min != 0 || c->t_now != c->pend_t0 + g.d_min)
       return fail(c, SD_ESTATE, "no completed slice to deliver");
@@ -1090,29 +1112,16 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
                   (long long)(t0 + g.d_min), (long long)c->t_now);
     if (t0 + g.d_min + g.d_max > c->t_now + g.ring_len)
       return fail(c, SD_EINVAL, "arrivals beyond the ring (t0 %lld)", (long long)t0);
-    // pack (src << 5 | lag) into a scratch list: reuse the raster-free path
-    if (n > 0) {
-      HIP_TRY(c, hipMalloc((void**)&packed, (size_t)n * 4 + 256));
-      d_n = (int32_t*)((char*)packed + (size_t)n * 4);
-      std::vector<uint32_t> hs((size_t)n);
-      std::vector<uint8_t> hl((size_t)n);
-      HIP_TRY(c, hipMemcpyAsync(hs.data(), d_src, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(hl.data(), d_lag, (size_t)n, hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      for (int64_t i = 0; i < n; ++i) {
-        if ((int64_t)hs[i] >= c->n_src || hl[i] >= g.d_min) {
-          (void)hipFree(packed);
-          return fail(c, SD_EINVAL, "entry %lld: src %u / lag %u out of range", (long long)i,
-                      hs[i], (unsigned)hl[i]);
-        }
-        hs[i] = (hs[i] << 5) | hl[i];
-      }
-      const int32_t nn = (int32_t)n;
-      HIP_TRY(c, hipMemcpyAsync(packed, hs.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(d_n, &nn, 4, hipMemcpyHostToDevice, c->stream));
-    }
-    a.in_list = packed;
-    a.in_cnt = d_n;
+    // pack (src << 5 | lag) into the context's external list on the device;
+    // invalid entries deliver nothing and raise a sticky flag
+    if (n > cap)
+      return fail(c, SD_EINVAL, "%lld entries exceed the list capacity %lld", (long long)n,
+                  (long long)cap);
+    if (n > 0)
+      HIP_TRY(c, launch_pack_list(c->stream, d_src, d_lag, n, c->n_src, g.d_min, list, list_cnt,
+                                  c->overflow));
+    a.in_list = list;
+    a.in_cnt = list_cnt;
     a.in_cap = n;
     if (n == 0) a.do_deliver = 0;
   }
@@ -1131,10 +1140,6 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
                                 std::max(c->rb_hi, w_lo), w_lo + g.d_max));
   }
   c->rb_hi = std::max(c->rb_hi, w_lo + g.d_max);
-  if (packed) {
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipFree(packed));
-  }
   if (own) c->pend_open = false;
   return SD_OK;
 }
@@ -1294,6 +1299,7 @@ sd_status sd_get_stats(sd_ctx* c, sd_stats* out) {
   out->spikes_recorded = (int64_t)std::min<unsigned long long>(cnt[3], (unsigned long long)c->rec_cap);
   out->slices = c->slices;
   out->overflow = ov;
+  if (ov & 12) return fail(c, SD_EINVAL, "an external spike list held invalid entries (flags %d)", ov);
   return ov ? SD_EOVERFLOW : SD_OK;
 }
 

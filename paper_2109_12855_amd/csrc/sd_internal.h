@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/sdeliver.h"
+
 namespace sd {
 
 enum { STREAM_SYN = 1, STREAM_INIT = 2, STREAM_DRIVE = 3, STREAM_SRC = 4 };
@@ -43,7 +45,7 @@ struct SliceArgs {
   // BF16 residual (residual forms) or the weight itself (FP32, BF16); the
   // pairs hold the scale 2^s of the LDS window (count mode: m1 = 0, m0 = 2^s)
   float wm0_e, wm1_e, wm0_i, wm1_i;
-  double fx_inv;           // 2^-s
+  float fx_inv;            // 2^-s
   int32_t grid_per_xcd;    // blocks handled by one XCD (ceil(NB / 8))
   // delivery
   int32_t do_deliver;
@@ -92,7 +94,8 @@ struct SliceArgs {
   unsigned long long* ev_count;    // synaptic events delivered
   unsigned long long* spk_in_count;// spike entries delivered
   unsigned long long* spk_count;   // spikes emitted
-  int32_t* overflow;               // bit 0: list, bit 1: raster, bit 2: bad entry
+  int32_t* overflow;               // bit 0: list, bit 1: raster, bit 2: bad entry,
+                                   // bit 3: bad entry in an external list
 };
 
 struct BuildArgs {
@@ -188,10 +191,24 @@ hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a);
 hipError_t launch_bin(hipStream_t s, const BinArgs& a, int32_t P, size_t lds, bool w8);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);
+// pack and validate an external spike list (see k_pack_list); cnt receives n
+hipError_t launch_pack_list(hipStream_t s, const uint32_t* src, const uint8_t* lag, int64_t n,
+                            int64_t n_src, int32_t Dmin, uint32_t* out, int32_t* cnt,
+                            int32_t* flag);
 hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
                               int32_t n_steps, int32_t Dmin, uint32_t thr, int32_t* cnt);
 hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_t t0,
                              int32_t n_steps, int32_t Dmin, uint32_t thr, const int64_t* off,
                              int32_t* cursor, uint32_t* list);
+
+// host library internals used by other translation units (sd_api.cpp)
+// sd_deliver_spikes with the packed list (cap entries) and its count in
+// caller-chosen device memory
+sd_status deliver_external(sd_ctx* c, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
+                           int64_t t0, uint32_t* list, int32_t* list_cnt, int64_t cap);
+// record an error message on the context and return st
+sd_status set_error(sd_ctx* c, sd_status st, const char* msg);
+// device the context was created on
+int ctx_device(const sd_ctx* c);
 
 }  // namespace sd

@@ -31,6 +31,8 @@
 //   resolving one spike read neighbouring words.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sd_internal.h"
 
 namespace sd {
@@ -733,8 +735,12 @@ __device__ __forceinline__ void syn_decode(const SynRaw<WF>& x, int32_t j0, int 
   v = (int)fmaf(m1, w, m0);  // conversion truncates toward zero
 }
 
-__device__ __forceinline__ float from_fixed(long long q, double inv) {
-  return (float)((double)q * inv);
+// Window cell (64-bit fixed point, quantum inv = 2^-s) to FP32: the
+// integer is rounded once to the nearest FP32 (ties to even; the int64 ->
+// FP32 conversion is correctly rounded), and the power-of-two scale is
+// exact.  Same value as an FP64 product rounded to FP32, with no FP64.
+__device__ __forceinline__ float from_fixed(long long q, float inv) {
+  return (float)q * inv;
 }
 
 template <bool V> struct BoolC { static constexpr bool value = V; };
@@ -1169,7 +1175,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // keep the flush running long after the update.
   auto flush_rows = [&](int t0, int stride) {
     constexpr int kFl = 8;
-    const double inv = a.fx_inv;
+    const float inv = a.fx_inv;
     int64_t t_first = a.t_upd + a.n_upd;
     if (t_first < w_lo) t_first = w_lo;
     const int nrows = (int)(w_lo + a.Dmax - t_first);
@@ -1215,7 +1221,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     constexpr bool kRegs = decltype(regs_tag)::value;
     const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
     const float P32 = a.prop[4], P33 = a.prop[5], P30Ie = a.prop[6], insc = a.prop[7];
-    const double inv = a.fx_inv;
+    const float inv = a.fx_inv;
     for (int n = tid; n < nb; n += kSliceThreads) {
       const int64_t gn = j0 + n;
       float V, y1 = 0.f, y2 = 0.f;
@@ -1429,6 +1435,29 @@ __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64
   rb[(t % L) * N + (i % N)] = 0.f;
 }
 
+// An external spike list (separate source and lag arrays) packed into the
+// delivery's entry format (src << 5 | lag), validated on the device: an
+// entry with src >= n_src or lag >= d_min becomes kBadEntry (delivers
+// nothing) and sets bit 3 of the sticky flag word.  Workgroup 0's first
+// thread stores the entry count, so the list needs no host round trip and
+// no memset (the count is in place before any later kernel on the stream
+// reads it).
+constexpr uint32_t kBadEntry = 0xffffffffu;  // src 2^27 - 1 >= n_src, lag 31
+__global__ void k_pack_list(const uint32_t* src, const uint8_t* lag, int64_t n, int64_t n_src,
+                            int32_t Dmin, uint32_t* out, int32_t* cnt, int32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t s = src[i];
+    const uint32_t l = lag[i];
+    const bool ok = (int64_t)s < n_src && (int32_t)l < Dmin;
+    out[i] = ok ? (s << 5) | l : kBadEntry;
+    bad |= !ok;
+  }
+  if (bad) atomicOr(flag, 8);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cnt = (int32_t)n;
+}
+
 __device__ __forceinline__ uint32_t half32(const uint64_t w[4], int64_t t) {
   const uint64_t x = w[(t & 7) >> 1];
   return (t & 1) ? (uint32_t)(x >> 32) : (uint32_t)x;
@@ -1633,6 +1662,16 @@ hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int6
   const int64_t n = (t_hi - t_lo) * N;
   hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rb, N, L,
                      t_lo, t_hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_list(hipStream_t s, const uint32_t* src, const uint8_t* lag, int64_t n,
+                            int64_t n_src, int32_t Dmin, uint32_t* out, int32_t* cnt,
+                            int32_t* flag) {
+  const int64_t want = (n + 255) / 256;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+  hipLaunchKernelGGL(k_pack_list, dim3(grid), dim3(256), 0, s, src, lag, n, n_src, Dmin, out,
+                     cnt, flag);
   return hipGetLastError();
 }
 

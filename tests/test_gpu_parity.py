@@ -195,18 +195,36 @@ def test_replay_wraps_around_ring():
 
 
 def test_replay_empty_list_and_errors():
+    """Empty lists deliver nothing.  Invalid entries are caught on the device:
+    they deliver nothing, the valid entries of the same list are delivered,
+    and the next synchronising call reports SD_EINVAL (sticky flag)."""
     cfg = _tiny_cases()[0]
     net = sdeliver.Net(cfg).build()
     z = torch.zeros(0, dtype=torch.int32, device="cuda")
     zl = torch.zeros(0, dtype=torch.uint8, device="cuda")
     net.deliver(z, zl, 0)
     assert not net.ring().any()
-    with pytest.raises(sdeliver.SdError):
-        s, l = _dev(np.array([5], np.uint32), np.array([cfg["d_min"]], np.uint8))
-        net.deliver(s, l, 0)  # lag >= d_min
-    with pytest.raises(sdeliver.SdError):
-        s, l = _dev(np.array([10**6], np.uint32), np.array([0], np.uint8))
-        net.deliver(s, l, 0)  # source out of range
+    assert net.stats()["overflow"] == 0
+    n = cfg["n_exc"] + cfg["n_inh"]
+    for bad_src, bad_lag in ((5, cfg["d_min"]), (10**6, 0), (n, 1)):
+        net = sdeliver.Net(cfg).build()
+        ref = oracle.Net(cfg)
+        net.set_count_mode(True)
+        src = np.array([3, bad_src, 7], np.uint32)
+        lag = np.array([0, bad_lag, 2], np.uint8)
+        net.deliver(*_dev(src, lag), 0)
+        ref.deliver(src[[0, 2]], lag[[0, 2]], 0)
+        assert np.array_equal(net.ring().astype(np.int64), ref.counts().astype(np.int64))
+        with pytest.raises(sdeliver.SdError) as e:
+            net.stats()
+        assert e.value.status == sdeliver.SD_EINVAL
+    # a list longer than the context's capacity is rejected at the call
+    net = sdeliver.Net(cfg).build()
+    big = net.sizes["n_blocks"] * net.sizes["block_neurons"] * cfg["d_min"] + 1
+    s, l = _dev(np.zeros(big, np.uint32), np.zeros(big, np.uint8))
+    with pytest.raises(sdeliver.SdError) as e:
+        net.deliver(s, l, 0)
+    assert e.value.status == sdeliver.SD_EINVAL
 
 
 def test_two_deliveries_accumulate():
