@@ -118,6 +118,9 @@ def lib():
         L.or_open_loop_spikes.argtypes = [P(Config), C.c_int64, C.c_int32, C.c_void_p,
                                           C.c_void_p, C.c_int64]
         L.or_open_loop_spikes.restype = C.c_int64
+        L.or_open_loop_spikes_range.argtypes = [P(Config), C.c_int64, C.c_int32, C.c_int64,
+                                                C.c_int64, C.c_void_p, C.c_void_p, C.c_int64]
+        L.or_open_loop_spikes_range.restype = C.c_int64
         L.or_read_vpre.argtypes = [C.c_void_p, C.c_void_p]
         L.or_drive_count.argtypes = [C.c_void_p, C.c_int64, C.c_int64]
         L.or_drive_count.restype = C.c_int32
@@ -177,14 +180,29 @@ def ref_steps(cfg: dict) -> int:
     return lib().or_ref_steps(C.byref(c))
 
 
-def open_loop_spikes(cfg: dict, t0: int, n_steps: int, cap: int = 1 << 22):
+def open_loop_spikes(cfg: dict, t0: int, n_steps: int, cap: int = 1 << 22, s_lo=None,
+                     s_hi=None):
+    """Spikes of the open-loop virtual sources in steps [t0, t0 + n_steps),
+    (lag, src) order; with s_lo / s_hi only those of sources [s_lo, s_hi)."""
     c = make_config(cfg)
     src = np.zeros(cap, np.uint32)
     lag = np.zeros(cap, np.uint8)
-    n = lib().or_open_loop_spikes(C.byref(c), int(t0), int(n_steps), _ptr(src), _ptr(lag), cap)
+    if s_lo is None and s_hi is None:
+        n = lib().or_open_loop_spikes(C.byref(c), int(t0), int(n_steps), _ptr(src), _ptr(lag), cap)
+    else:
+        n = lib().or_open_loop_spikes_range(C.byref(c), int(t0), int(n_steps), int(s_lo),
+                                            int(s_hi), _ptr(src), _ptr(lag), cap)
     if n < 0:
         raise RuntimeError("open-loop spike capacity exceeded")
     return src[:n].copy(), lag[:n].copy()
+
+
+def _merge_lag_src(parts):
+    """Concatenate (src, lag) lists and order the result by (lag, src)."""
+    src = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.uint32)
+    lag = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.uint8)
+    order = np.lexsort((src, lag))
+    return src[order], lag[order]
 
 
 class Net:
@@ -301,3 +319,94 @@ class Net:
 
     def drive_count(self, j: int, t: int) -> int:
         return lib().or_drive_count(self._h, int(j), int(t))
+
+
+class Partitioned:
+    """The oracle split into target ranges that advance together, one host
+    thread per range (ctypes releases the GIL, so the ranges run on separate
+    cores).
+
+    Each range is an ordinary oracle ``Net`` holding targets [lo, hi) with
+    every source (target sampling).  The cycle is the paper's: every d_min
+    steps the ranges are updated, their spikes are gathered into one list in
+    (lag, src) order -- the order a single oracle keeps its pending slice in
+    -- and that list is delivered to every range (Sec. 2.1: update,
+    communicate, deliver).  Open loop, the list is the virtual sources'
+    spikes, drawn in source ranges on the same threads.  Every range adds
+    the same weights in the same order as an unsplit oracle, so states,
+    rings and spikes equal the unsplit oracle's exactly.  ``targets`` limits
+    the held neurons to [0, targets) (open loop only: closed loop needs
+    every neuron's spikes)."""
+
+    def __init__(self, cfg: dict, n_parts: int, threads: int | None = None,
+                 targets: int | None = None):
+        from concurrent.futures import ThreadPoolExecutor
+
+        self.cfg = dict(cfg)
+        n = int(cfg["n_exc"] + cfg["n_inh"])
+        self.open = int(cfg.get("n_src_exc", 0)) > 0
+        if targets is not None and targets < n and not self.open:
+            raise ValueError("a closed-loop net needs every target")
+        self.n = n if targets is None else int(targets)
+        self.bounds = np.linspace(0, self.n, n_parts + 1).astype(np.int64)
+        self.pool = ThreadPoolExecutor(max_workers=threads or n_parts)
+        self.threads = threads or n_parts
+        lo_hi = [(int(a), int(b)) for a, b in zip(self.bounds[:-1], self.bounds[1:]) if b > a]
+        self.parts = list(self.pool.map(lambda r: Net(self.cfg, tgt_lo=r[0], tgt_hi=r[1]), lo_hi))
+        self.d_min = int(cfg["d_min"])
+        self.t_now = 0
+        self.pend = None          # (src, lag, t0) of the open slice, closed loop
+        self.n_src = self.parts[0].n_src
+
+    def _open_loop_list(self, t0: int):
+        n_src = self.n_src
+        cuts = np.linspace(0, n_src, self.threads + 1).astype(np.int64)
+        cap = int(n_src * self.d_min * 0.01) + 4096
+        lists = list(self.pool.map(
+            lambda r: open_loop_spikes(self.cfg, t0, self.d_min, cap=cap, s_lo=r[0], s_hi=r[1]),
+            [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]))
+        return _merge_lag_src(lists)
+
+    def simulate(self, n_steps: int):
+        """Advance n_steps; returns the spikes (step, id) of the held
+        neurons, ordered by (step, id)."""
+        out_st, out_id = [], []
+        left = int(n_steps)
+        while left > 0:
+            in_slice = self.t_now % self.d_min
+            if in_slice == 0 and self.t_now > 0:
+                t0 = self.t_now - self.d_min
+                if self.open:
+                    src, lag = self._open_loop_list(t0)
+                else:
+                    src, lag = self.pend[0], self.pend[1]
+                list(self.pool.map(lambda p: p.deliver(src, lag, t0), self.parts))
+            if in_slice == 0:
+                self.pend = (np.zeros(0, np.uint32), np.zeros(0, np.uint8))
+            m = min(left, self.d_min - in_slice)
+            res = list(self.pool.map(lambda p: p.update(m, cap=p.n_local * m + 1), self.parts))
+            st = np.concatenate([r[0] for r in res])
+            idx = np.concatenate([r[1] for r in res])
+            if not self.open and len(st):
+                slice0 = self.t_now - in_slice
+                self.pend = _merge_lag_src([self.pend, (idx.astype(np.uint32),
+                                                        (st - slice0).astype(np.uint8))])
+            out_st.append(st)
+            out_id.append(idx)
+            self.t_now += m
+            left -= m
+        st = np.concatenate(out_st) if out_st else np.zeros(0, np.int64)
+        idx = np.concatenate(out_id) if out_id else np.zeros(0, np.uint32)
+        order = np.lexsort((idx, st))
+        return st[order], idx[order]
+
+    def state(self):
+        sts = [p.state() for p in self.parts]
+        return {k: np.concatenate([s[k] for s in sts]) for k in sts[0]}
+
+    def ring(self):
+        return np.concatenate([p.ring() for p in self.parts], axis=1)
+
+    def close(self):
+        self.parts = []
+        self.pool.shutdown()

@@ -478,15 +478,18 @@ int64_t or_update(or_net* n, int64_t n_steps, int64_t* spk_step, uint32_t* spk_i
   return update_steps(n, n_steps, 0, spk_step, spk_id, cap, 0);
 }
 
-int64_t or_open_loop_spikes(const or_config* c, int64_t t0, int32_t n_steps, uint32_t* src,
-                            uint8_t* lag, int64_t cap) {
-  int64_t ns = c->n_src_exc + c->n_src_inh;
+/* Open-loop virtual sources [s_lo, s_hi): source s fires at step t when the
+ * 32-bit uniform of step t from Philox (seed, SRC) at counter (s, t / 8) lies
+ * below floor(2^32 p), p = 1 - exp(-rate h) the probability of a spike in one
+ * step.  Spikes of steps [t0, t0 + n_steps) in (lag, src) order. */
+int64_t or_open_loop_spikes_range(const or_config* c, int64_t t0, int32_t n_steps, int64_t s_lo,
+                                  int64_t s_hi, uint32_t* src, uint8_t* lag, int64_t cap) {
   double p = -expm1(-c->src_rate_hz * c->h * 1e-3);
   uint64_t thr = (uint64_t)floor(p * 4294967296.0);
   int64_t n = 0;
   for (int32_t l = 0; l < n_steps; ++l) {
     int64_t t = t0 + l;
-    for (int64_t s = 0; s < ns; ++s) {
+    for (int64_t s = s_lo; s < s_hi; ++s) {
       uint64_t r[4];
       philox(c->seed, OR_STREAM_SRC, (uint64_t)s, (uint64_t)(t >> 3), r);
       if ((uint64_t)half32(r, t) < thr) {
@@ -498,6 +501,11 @@ int64_t or_open_loop_spikes(const or_config* c, int64_t t0, int32_t n_steps, uin
     }
   }
   return n;
+}
+
+int64_t or_open_loop_spikes(const or_config* c, int64_t t0, int32_t n_steps, uint32_t* src,
+                            uint8_t* lag, int64_t cap) {
+  return or_open_loop_spikes_range(c, t0, n_steps, 0, c->n_src_exc + c->n_src_inh, src, lag, cap);
 }
 
 /* The simulation cycle (Sec. 1, Sec. 2.1): slices of d_min steps aligned on

@@ -99,6 +99,9 @@ int64_t or_pending(const or_net* n, uint32_t* src, uint8_t* lag, int64_t cap, in
 /* open-loop virtual sources: spikes of steps [t0, t0+n_steps), (lag, src) order */
 int64_t or_open_loop_spikes(const or_config* c, int64_t t0, int32_t n_steps,
                             uint32_t* src, uint8_t* lag, int64_t cap);
+/* the same for virtual sources [s_lo, s_hi) only                              */
+int64_t or_open_loop_spikes_range(const or_config* c, int64_t t0, int32_t n_steps, int64_t s_lo,
+                                  int64_t s_hi, uint32_t* src, uint8_t* lag, int64_t cap);
 /* membrane potential of every held neuron just before the threshold test of
  * the last updated step (before any reset)                                   */
 void or_read_vpre(const or_net* n, double* out);

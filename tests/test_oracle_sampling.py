@@ -122,3 +122,49 @@ def test_sampling_uses_global_target_ids():
     a = oracle.Net(dict(cfg, tgt_lo=0, tgt_hi=50)).target_major()[0]
     b = oracle.Net(dict(cfg, tgt_lo=50, tgt_hi=100)).target_major()[0]
     assert not np.array_equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# source ranges of the open-loop draws, and the partitioned driver
+# --------------------------------------------------------------------------
+def test_open_loop_source_ranges_cover_the_full_draw():
+    cfg = dict(W.ALPHA_BRAIN_SHARE, n_src_exc=40000, n_src_inh=10000, src_rate_hz=80.0, seed=4)
+    full = oracle.open_loop_spikes(cfg, 13, 10)
+    cuts = [0, 1, 17000, 17001, 33333, 50000]
+    parts = [oracle.open_loop_spikes(cfg, 13, 10, s_lo=a, s_hi=b) for a, b in zip(cuts, cuts[1:])]
+    for (s, l), a, b in zip(parts, cuts, cuts[1:]):
+        assert np.all((s >= a) & (s < b))
+    src, lag = oracle._merge_lag_src(parts)
+    assert np.array_equal(src, full[0]) and np.array_equal(lag, full[1])
+
+
+@pytest.mark.parametrize("model,n,k,parts", [(0, 60, 12, 1), (0, 60, 12, 4), (1, 90, 20, 7)])
+def test_partitioned_closed_loop_equals_single_oracle(model, n, k, parts):
+    cfg = W.tiny(model=model, n=n, k=k, seed=31, d_lo=4, d_hi=9)
+    one = oracle.Net(cfg)
+    st, idx = one.simulate(347)
+    assert len(st) > 20
+    part = oracle.Partitioned(cfg, parts, threads=3)
+    pst, pid = part.simulate(100)
+    pst2, pid2 = part.simulate(247)
+    assert np.array_equal(np.concatenate([pst, pst2]), st)
+    assert np.array_equal(np.concatenate([pid, pid2]), idx)
+    ps, os_ = part.state(), one.state()
+    for key in ("V", "y1", "y2", "r"):
+        assert np.array_equal(ps[key], os_[key])
+    assert np.array_equal(part.ring(), one.ring())
+    part.close()
+
+
+def test_partitioned_open_loop_target_subset():
+    cfg = _open_cfg(seed=17)
+    one = oracle.Net(dict(cfg, tgt_hi=250))
+    st, idx = one.simulate(123)
+    assert len(st) > 10
+    part = oracle.Partitioned(cfg, 3, threads=3, targets=250)
+    pst, pid = part.simulate(123)
+    assert np.array_equal(pst, st) and np.array_equal(pid, idx)
+    assert np.array_equal(part.ring(), one.ring())
+    part.close()
+    with pytest.raises(ValueError):
+        oracle.Partitioned(W.tiny(model=0, n=40, k=8), 2, targets=20)
