@@ -190,6 +190,17 @@ sd_status sd_update_neurons(sd_ctx* ctx, int32_t n_steps);
  * [t_now, t_now + ring_len); otherwise SD_EINVAL at the call. */
 sd_status sd_deliver_spikes(sd_ctx* ctx, const uint32_t* d_src, const uint8_t* d_lag, int64_t n,
                             int64_t t0);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * delivery as sd_deliver_spikes, with the packed list and its count in a
+ * fixed device array of the library (2^20 entries, 4 MiB, one copy per GPU,
+ * held until the process ends) instead of the context's buffer.  The call
+ * allocates and frees nothing.  n above 2^20 (or above the context's list
+ * capacity): SD_EINVAL.  All calls on one GPU share that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams or host threads) race on it and must be ordered by the caller. */
+sd_status sd_deliver_spikes_noalloc(sd_ctx* ctx, const uint32_t* d_src, const uint8_t* d_lag,
+                                    int64_t n, int64_t t0);
 /* Deliver the context's own completed slice (its spikes emitted in the last
  * d_min steps); SD_ESTATE when no completed slice is pending. */
 sd_status sd_deliver_pending(sd_ctx* ctx);

@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libsdeliver.so")
 CPU_LIB = os.path.join(HERE, "libsdcpu.so")
 CPU_SOURCES = [os.path.join(HERE, "cpu", "sd_cpu.c")]
 SOURCES = [os.path.join(CSRC, "sd_api.cpp"), os.path.join(CSRC, "sd_autotune.cpp"),
-           os.path.join(CSRC, "sd_kernels.hip")]
+           os.path.join(CSRC, "sd_kernels.hip"), os.path.join(CSRC, "sd_noalloc.hip")]
 ARCH = os.environ.get("SD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

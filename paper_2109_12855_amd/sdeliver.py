@@ -83,7 +83,7 @@ EXPORTS = (
     "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
     "sd_batch_size", "sd_batch_member", "sd_batch_build", "sd_batch_simulate_steps",
     "sd_batch_simulate", "sd_batch_set_graph", "sd_batch_graph_launches", "sd_save_state",
-    "sd_load_state", "sd_autotune",
+    "sd_load_state", "sd_autotune", "sd_deliver_spikes_noalloc",
 )
 
 _lib = None
@@ -106,6 +106,7 @@ def lib():
         "sd_build_connections": ([vp], i32),
         "sd_update_neurons": ([vp, i32], i32),
         "sd_deliver_spikes": ([vp, vp, vp, i64, i64], i32),
+        "sd_deliver_spikes_noalloc": ([vp, vp, vp, i64, i64], i32),
         "sd_deliver_pending": ([vp], i32),
         "sd_simulate": ([vp, dbl], i32),
         "sd_simulate_steps": ([vp, i64], i32),
@@ -278,6 +279,13 @@ class Net:
         else:
             rc = lib().sd_deliver_spikes(self._h, _ptr(src), _ptr(lag), int(src.numel()), int(t0))
         self._check(rc, "sd_deliver_spikes")
+
+    def deliver_noalloc(self, src, lag, t0: int = 0):
+        """Deliver a device spike list with the library's fixed scratch array
+        (sd_deliver_spikes_noalloc: no allocation; at most 2^20 entries)."""
+        rc = lib().sd_deliver_spikes_noalloc(self._h, _ptr(src), _ptr(lag), int(src.numel()),
+                                             int(t0))
+        self._check(rc, "sd_deliver_spikes_noalloc")
 
     def simulate(self, t_ms: float):
         self._check(lib().sd_simulate(self._h, float(t_ms)), "sd_simulate")
