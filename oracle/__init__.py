@@ -54,6 +54,10 @@ class Config(C.Structure):
         ("src_rate_hz", C.c_double),
         ("seed", C.c_uint64),
         ("tgt_lo", C.c_int64), ("tgt_hi", C.c_int64),
+        ("plastic", C.c_int32),
+        ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
+        ("stdp_a_plus", C.c_double), ("stdp_a_minus", C.c_double),
+        ("stdp_w_max", C.c_double),
     ]
 
 
@@ -124,6 +128,10 @@ def lib():
         L.or_read_vpre.argtypes = [C.c_void_p, C.c_void_p]
         L.or_drive_count.argtypes = [C.c_void_p, C.c_int64, C.c_int64]
         L.or_drive_count.restype = C.c_int32
+        L.or_stdp_update.argtypes = [P(Config), C.c_double, C.c_int64, C.c_int64, C.c_int64,
+                                     C.c_int32]
+        L.or_stdp_update.restype = C.c_double
+        L.or_read_weights.argtypes = [C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -173,6 +181,12 @@ def bf16_round(x: float) -> float:
 def decode_weight(cfg: dict, is_inh: bool, w32: float) -> float:
     c = make_config(cfg)
     return lib().or_decode_weight(C.byref(c), int(is_inh), float(w32))
+
+
+def stdp_update(cfg: dict, w: float, t_pre: int, t_prev: int, t_last: int, d: int) -> float:
+    """One plastic weight update (see or_stdp_update); -1 marks no spike."""
+    c = make_config(cfg)
+    return lib().or_stdp_update(C.byref(c), float(w), int(t_pre), int(t_prev), int(t_last), int(d))
 
 
 def ref_steps(cfg: dict) -> int:
@@ -317,6 +331,13 @@ class Net:
         lib().or_read_vpre(self._h, _ptr(out))
         return out
 
+    def weights(self) -> np.ndarray:
+        """Current weights of the source-major table (its (src, target, k)
+        order); plastic nets change them at every delivery."""
+        out = np.zeros(self.n_syn, np.float64)
+        lib().or_read_weights(self._h, _ptr(out))
+        return out
+
     def drive_count(self, j: int, t: int) -> int:
         return lib().or_drive_count(self._h, int(j), int(t))
 
@@ -335,8 +356,8 @@ class Partitioned:
     spikes, drawn in source ranges on the same threads.  Every range adds
     the same weights in the same order as an unsplit oracle, so states,
     rings and spikes equal the unsplit oracle's exactly.  ``targets`` limits
-    the held neurons to [0, targets) (open loop only: closed loop needs
-    every neuron's spikes)."""
+    the held neurons to [0, targets) or to a (lo, hi) range (open loop only:
+    closed loop needs every neuron's spikes)."""
 
     def __init__(self, cfg: dict, n_parts: int, threads: int | None = None,
                  targets: int | None = None):
@@ -345,10 +366,12 @@ class Partitioned:
         self.cfg = dict(cfg)
         n = int(cfg["n_exc"] + cfg["n_inh"])
         self.open = int(cfg.get("n_src_exc", 0)) > 0
-        if targets is not None and targets < n and not self.open:
+        lo, hi = (0, n) if targets is None else (
+            (0, int(targets)) if np.isscalar(targets) else (int(targets[0]), int(targets[1])))
+        if (lo, hi) != (0, n) and not self.open:
             raise ValueError("a closed-loop net needs every target")
-        self.n = n if targets is None else int(targets)
-        self.bounds = np.linspace(0, self.n, n_parts + 1).astype(np.int64)
+        self.lo, self.hi = lo, hi
+        self.bounds = np.linspace(lo, hi, n_parts + 1).astype(np.int64)
         self.pool = ThreadPoolExecutor(max_workers=threads or n_parts)
         self.threads = threads or n_parts
         lo_hi = [(int(a), int(b)) for a, b in zip(self.bounds[:-1], self.bounds[1:]) if b > a]
@@ -406,6 +429,9 @@ class Partitioned:
 
     def ring(self):
         return np.concatenate([p.ring() for p in self.parts], axis=1)
+
+    def vpre(self):
+        return np.concatenate([p.vpre() for p in self.parts])
 
     def close(self):
         self.parts = []

@@ -222,3 +222,80 @@ def open_loop_spikes(cfg: dict, t0: int, n_steps: int):
             src.append(int(s))
             lag.append(l)
     return np.array(src, np.uint32), np.array(lag, np.uint8)
+
+
+def simulate_plastic(cfg: dict, n_steps: int):
+    """Dense time-stepped simulation with plastic excitatory synapses.
+
+    A second formulation of the plasticity reading: synapses are held target-
+    major (as drawn) with per-synapse weights; when a source fires at step t
+    each of its excitatory synapses (j, d) is updated at once from the raster
+    so far -- the latest spike of j at or before t - d, and the source's
+    previous spike -- and the updated weight is scheduled to arrive at j at
+    step t + d.  No ring buffers, no slices, no source-major table."""
+    n = cfg["n_exc"] + cfg["n_inh"]
+    src, dly, widx, w = connections(cfg)
+    w = w.copy()
+    P = propagators(cfg)
+    thr = poisson_thresholds(cfg["drive_rate_hz"] * cfg["h"] * 1e-3)
+    ref = int(round(cfg["t_ref"] / cfg["h"]))
+    V = initial_v(cfg, n)
+    y1 = np.zeros(n)
+    y2 = np.zeros(n)
+    r = np.zeros(n, np.int64)
+    S = np.zeros((n_steps, n), bool)
+    arrive = np.zeros((n_steps + cfg["d_max"] + 1, n))
+    last_pre = np.full(n, -1, np.int64)
+    by_src = {}
+    for j in range(n):
+        for k in range(src.shape[1]):
+            by_src.setdefault(int(src[j, k]), []).append((j, k))
+    h = cfg["h"]
+    spikes = []
+    e_over_ts = math.e / cfg["tau_syn"]
+    drive_cache = {}
+    for t in range(n_steps):
+        x = arrive[t]
+        fired = []
+        for j in range(n):
+            key = (j, t >> 3)
+            if key not in drive_cache:
+                drive_cache[key] = philox_words(cfg["seed"], STREAM_DRIVE, j, t >> 3)
+            wd = drive_cache[key][(t & 7) >> 1]
+            u = (wd >> 32) if (t & 1) else (wd & 0xFFFFFFFF)
+            drive = sum(1 for T in thr if u >= T) * cfg["drive_w"]
+            if cfg["model"] == 0:
+                if r[j] > 0:
+                    r[j] -= 1
+                else:
+                    V[j] = cfg["e_l"] + P["P33"] * (V[j] - cfg["e_l"]) + P["P30"] * cfg["i_e"] + x[j] + drive
+            else:
+                a1, a2 = y1[j], y2[j]
+                if r[j] == 0:
+                    V[j] = (cfg["e_l"] + P["P31"] * a1 + P["P32"] * a2 + P["P33"] * (V[j] - cfg["e_l"])
+                            + P["P30"] * cfg["i_e"])
+                else:
+                    r[j] -= 1
+                y2[j] = P["P21"] * a1 + P["P22"] * a2
+                y1[j] = P["P11"] * a1 + e_over_ts * (x[j] + drive)
+            if V[j] >= cfg["v_th"]:
+                V[j] = cfg["v_reset"]
+                r[j] = ref
+                S[t, j] = True
+                spikes.append((t, j))
+                fired.append(j)
+        for s in fired:
+            for (j, k) in by_src.get(s, []):
+                d = int(dly[j, k])
+                if s < cfg["n_exc"]:
+                    seen = np.flatnonzero(S[: t - d + 1, j]) if t - d >= 0 else []
+                    if len(seen):
+                        tl = int(seen[-1])
+                        if last_pre[s] >= 0 and tl + d > last_pre[s]:
+                            w[j, k] = min(cfg["stdp_w_max"], w[j, k] + cfg["stdp_a_plus"] *
+                                          math.exp(-(tl + d - last_pre[s]) * h / cfg["stdp_tau_plus"]))
+                        w[j, k] = max(0.0, w[j, k] - cfg["stdp_a_minus"] *
+                                      math.exp(-(t - tl - d) * h / cfg["stdp_tau_minus"]))
+                arrive[t + d, j] += w[j, k]
+            last_pre[s] = t
+    return dict(spikes=spikes, w=w, src=src, dly=dly, V=V, y1=y1, y2=y2, r=r)

@@ -235,6 +235,13 @@ struct or_net {
   double* rb;               /* [L][n_local]                                  */
   uint32_t* cnt;            /* [L][n_local] events per cell                  */
   int64_t t_now;
+  /* plastic synapses: every spike step of each held neuron (full record),
+   * and each source's latest spike delivered so far */
+  int64_t** hist;
+  int64_t* hist_n;
+  int64_t* hist_cap;
+  int64_t* prev_pre;        /* [n_src], -1: none                              */
+  int64_t src_e_end;        /* sources below this id are excitatory           */
   /* pending slice: spikes emitted since slice start pend_t0, not delivered */
   int64_t pend_t0;
   int pend_open;
@@ -256,6 +263,9 @@ void or_net_destroy(or_net* n) {
   free(n->row); free(n->tgt); free(n->dly); free(n->w);
   free(n->V); free(n->y1); free(n->y2); free(n->r); free(n->vpre);
   free(n->rb); free(n->cnt); free(n->pend_src); free(n->pend_lag);
+  if (n->hist)
+    for (int64_t j = 0; j < n->n_local; ++j) free(n->hist[j]);
+  free(n->hist); free(n->hist_n); free(n->hist_cap); free(n->prev_pre);
   free(n);
 }
 
@@ -352,6 +362,14 @@ or_net* or_net_create(const or_config* cfg) {
   n->pend_cap = 1024;
   n->pend_src = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n->pend_cap);
   n->pend_lag = (uint8_t*)malloc((size_t)n->pend_cap);
+  n->src_e_end = src_e_n;
+  if (c->plastic) {
+    n->hist = (int64_t**)calloc(nl, sizeof(int64_t*));
+    n->hist_n = (int64_t*)calloc(nl, sizeof(int64_t));
+    n->hist_cap = (int64_t*)calloc(nl, sizeof(int64_t));
+    n->prev_pre = (int64_t*)malloc(sizeof(int64_t) * (size_t)n->n_src);
+    for (int64_t s = 0; s < n->n_src; ++s) n->prev_pre[s] = -1;
+  }
   return n;
 }
 
@@ -387,9 +405,47 @@ int32_t or_drive_count(const or_net* n, int64_t j, int64_t t) {
   return c;
 }
 
+/* Plastic synapses (Sec. 6): the update of an excitatory weight is driven by
+ * the presynaptic spike and computed when the spike is delivered, so that the
+ * weight the target sees is the updated one.  The whole delay d is taken to
+ * lie on the target side: the presynaptic spike of step t_pre meets the
+ * synapse at t_pre, a target spike of step t meets it at t + d.  The only
+ * target information read is the time of its last spike visible at the
+ * synapse, t_last (the latest target spike with t_last + d <= t_pre).  Pairs
+ * interact nearest-neighbour style with exponential windows:
+ *   potentiation: if that target spike came after the source's previous spike
+ *     t_prev (t_last + d > t_prev), it pairs with t_prev:
+ *       w += A+ exp(-(t_last + d - t_prev) h / tau+), then w = min(w, w_max);
+ *   depression: the current spike pairs with that target spike:
+ *       w -= A- exp(-(t_pre - t_last - d) h / tau-), then w = max(w, 0).
+ * No visible target spike: no change.  Steps are integers, times t h. */
+double or_stdp_update(const or_config* c, double w, int64_t t_pre, int64_t t_prev,
+                      int64_t t_last, int32_t d) {
+  if (t_last < 0) return w;
+  if (t_prev >= 0 && t_last + d > t_prev) {
+    w += c->stdp_a_plus * exp(-(double)(t_last + d - t_prev) * c->h / c->stdp_tau_plus);
+    if (w > c->stdp_w_max) w = c->stdp_w_max;
+  }
+  w -= c->stdp_a_minus * exp(-(double)(t_pre - t_last - d) * c->h / c->stdp_tau_minus);
+  if (w < 0.0) w = 0.0;
+  return w;
+}
+
+/* latest recorded spike of held neuron jl at or before step t, or -1 */
+static int64_t last_spike_upto(const or_net* n, int64_t jl, int64_t t) {
+  for (int64_t i = n->hist_n[jl] - 1; i >= 0; --i)
+    if (n->hist[jl][i] <= t) return n->hist[jl][i];
+  return -1;
+}
+
+void or_read_weights(const or_net* n, double* w) {
+  memcpy(w, n->w, sizeof(double) * (size_t)n->n_syn);
+}
+
 /* Alg. REF (Sec. 3.2): for each spike entry in the given order, walk the
  * source's target segment and add each weight into the target's ring buffer
- * at arrival step t0 + lag + delay. */
+ * at arrival step t0 + lag + delay.  Plastic nets first update each
+ * excitatory weight (or_stdp_update) and add the updated weight. */
 int or_deliver(or_net* n, const uint32_t* src, const uint8_t* lag, int64_t n_spk, int64_t t0,
                double* w_sum, int64_t* n_events) {
   const int64_t L = n->c.ring_len;
@@ -397,15 +453,24 @@ int or_deliver(or_net* n, const uint32_t* src, const uint8_t* lag, int64_t n_spk
   int64_t ne = 0;
   for (int64_t i = 0; i < n_spk; ++i) {
     if ((int64_t)src[i] >= n->n_src) { set_err("spike source out of range"); return -1; }
+    const int64_t t_pre = t0 + (int64_t)lag[i];
+    const int plastic_src = n->c.plastic && (int64_t)src[i] < n->src_e_end;
     for (int64_t e = n->row[src[i]]; e < n->row[src[i] + 1]; ++e) {
       int64_t t_arr = t0 + (int64_t)lag[i] + (int64_t)n->dly[e];
       if (t_arr < n->t_now || t_arr >= n->t_now + L) { set_err("arrival outside ring"); return -1; }
       int64_t cell = (t_arr % L) * n->n_local + ((int64_t)n->tgt[e] - n->lo);
+      if (plastic_src) {
+        const int64_t jl = (int64_t)n->tgt[e] - n->lo;
+        const int64_t t_last = last_spike_upto(n, jl, t_pre - (int64_t)n->dly[e]);
+        n->w[e] = or_stdp_update(&n->c, n->w[e], t_pre, n->prev_pre[src[i]], t_last,
+                                 (int32_t)n->dly[e]);
+      }
       n->rb[cell] += n->w[e];
       n->cnt[cell] += 1;
       ws += n->w[e];
       ne += 1;
     }
+    if (n->c.plastic) n->prev_pre[src[i]] = t_pre;
   }
   if (w_sum) *w_sum = ws;
   if (n_events) *n_events = ne;
@@ -456,6 +521,13 @@ static int64_t update_steps(or_net* n, int64_t m, int to_pending, int64_t* spk_s
       if (V >= c->v_th) {
         V = c->v_reset;
         n->r[jl] = n->ref_steps;
+        if (c->plastic) {
+          if (n->hist_n[jl] == n->hist_cap[jl]) {
+            n->hist_cap[jl] = n->hist_cap[jl] ? 2 * n->hist_cap[jl] : 16;
+            n->hist[jl] = (int64_t*)realloc(n->hist[jl], sizeof(int64_t) * (size_t)n->hist_cap[jl]);
+          }
+          n->hist[jl][n->hist_n[jl]++] = t;
+        }
         if (n_out >= 0) {
           if (n_out < cap) {
             if (spk_step) spk_step[n_out] = t;

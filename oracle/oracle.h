@@ -52,6 +52,13 @@ typedef struct {
   uint64_t seed;
   int64_t tgt_lo, tgt_hi;   /* generate targets [tgt_lo, tgt_hi) only (sampling);  */
                             /* tgt_hi = 0 means all local neurons                  */
+  /* Plastic synapses (Sec. 6: weight updates driven by presynaptic spikes,  */
+  /* computed when the weight becomes visible to the target, reading the     */
+  /* time of the target's last spike).  plastic = 0: static synapses.        */
+  int32_t plastic;
+  double stdp_tau_plus, stdp_tau_minus;  /* ms                                   */
+  double stdp_a_plus, stdp_a_minus;      /* weight units (pA / mV)               */
+  double stdp_w_max;                     /* excitatory weights stay in [0, w_max] */
 } or_config;
 
 typedef struct or_net or_net;
@@ -107,6 +114,12 @@ int64_t or_open_loop_spikes_range(const or_config* c, int64_t t0, int32_t n_step
 void or_read_vpre(const or_net* n, double* out);
 /* Poisson drive count of neuron j (global id) at step t                        */
 int32_t or_drive_count(const or_net* n, int64_t j, int64_t t);
+/* plastic synapses: the nearest-spike pair update of one excitatory weight at
+ * the delivery of a presynaptic spike (t_prev, t_last: -1 for none)           */
+double or_stdp_update(const or_config* c, double w, int64_t t_pre, int64_t t_prev,
+                      int64_t t_last, int32_t d);
+/* current weights of the source-major table (plastic nets change them)        */
+void or_read_weights(const or_net* n, double* w);
 
 #ifdef __cplusplus
 }

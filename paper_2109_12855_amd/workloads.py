@@ -103,6 +103,18 @@ WORKLOADS = {w["name"]: w for w in (DELTA_SMALL, ALPHA_112K, ALPHA_112K_BF16, AL
                                     ALPHA_112K_SHORT_DELAY)}
 
 
+def plastic(cfg: dict, a_plus: float = 0.01, a_minus: float = 0.0105, w_max: float = 2.0,
+            tau_plus: float = 20.0, tau_minus: float = 20.0) -> dict:
+    """The network with plastic excitatory synapses: amplitudes and the upper
+    weight bound as multiples of the mean excitatory weight, time constants
+    in ms (pair windows of the classic spike-timing experiments)."""
+    w = cfg["w_exc"]
+    out = dict(cfg, plastic=1, stdp_tau_plus=tau_plus, stdp_tau_minus=tau_minus,
+               stdp_a_plus=a_plus * w, stdp_a_minus=a_minus * w, stdp_w_max=w_max * w)
+    out["name"] = cfg.get("name", "net") + "_plastic"
+    return out
+
+
 def tiny(model: int = 0, n: int = 40, k: int = 8, seed: int = 7, d_lo: int | None = None,
          d_hi: int | None = None, wform: int = 0, w_cv: float | None = None, **over) -> dict:
     """A small balanced net of the same structure (80% E) for brute-force checks."""
