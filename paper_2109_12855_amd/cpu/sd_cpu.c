@@ -290,43 +290,83 @@ static int64_t deliver_ref(part* q, int32_t L, int64_t S, const del_job* j) {
   return ev;
 }
 
-/* Alg. bwTSRB*: spike entries in batches of b_ts (their segment starts and
- * sizes read first), the synapses of a batch's segments staged as (ring
- * buffer cell, weight) in batches of b_rb across segment boundaries; a full
- * batch is prefetched as a group, then its weights are added in order. */
-static int64_t deliver_bwtsrb(part* q, int32_t L, int64_t S, const del_job* j) {
-  int64_t lcid[SDC_MAX_BATCH], ts_size[SDC_MAX_BATCH];
-  int base[SDC_MAX_BATCH];
+/* Alg. bwTSRB* (Sec. 4.4), restated: spike entries are taken b_ts at a time,
+ * and the bounds of all their target segments are read before any synapse
+ * (hiding the latency of the segment lookups).  The batch's synapses are
+ * then visited as one flat sequence across segment boundaries and staged as
+ * (ring-buffer cell, weight) pairs; every b_rb pairs, the cells are
+ * prefetched together and the weights added in staging order.  Per cell the
+ * additions happen in the same order as in REF, so the sums are bitwise
+ * equal. */
+typedef struct {
+  int64_t first[SDC_MAX_BATCH], len[SDC_MAX_BATCH];  /* segment of each entry   */
+  int ring_base[SDC_MAX_BATCH];                      /* emission slot of each   */
+  int n;
+} spike_batch;
+
+/* position in the flat synapse sequence of a spike batch */
+typedef struct {
+  const spike_batch* sb;
+  int seg;
+  int64_t next;
+} flat_cursor;
+
+static int flat_next(flat_cursor* fc, int64_t* syn, int* ring_base) {
+  const spike_batch* sb = fc->sb;
+  while (fc->seg < sb->n && fc->next >= sb->first[fc->seg] + sb->len[fc->seg]) {
+    if (++fc->seg < sb->n) fc->next = sb->first[fc->seg];
+  }
+  if (fc->seg >= sb->n) return 0;
+  *syn = fc->next++;
+  *ring_base = sb->ring_base[fc->seg];
+  return 1;
+}
+
+typedef struct {
   double* cell[SDC_MAX_BATCH];
-  double wv[SDC_MAX_BATCH];
-  const int B_TS = j->b_ts, B_RB = j->b_rb;
-  int i = 0;
+  double add[SDC_MAX_BATCH];
+  int used, cap;
+} rb_stage;
+
+static void stage_flush(rb_stage* st, int prefetch) {
+  if (prefetch)
+    for (int r = 0; r < st->used; ++r) __builtin_prefetch(st->cell[r], 1, 3);
+  for (int r = 0; r < st->used; ++r) *st->cell[r] += st->add[r];
+  st->used = 0;
+}
+
+static void stage_put(rb_stage* st, double* cell, double w) {
+  st->cell[st->used] = cell;
+  st->add[st->used] = w;
+  if (++st->used == st->cap) stage_flush(st, 1);
+}
+
+static int64_t deliver_bwtsrb(part* q, int32_t L, int64_t S, const del_job* j) {
+  rb_stage st;
+  st.used = 0;
+  st.cap = j->b_rb;
   int64_t ev = 0;
-  for (int64_t l = 0; l < j->n_spk; l += B_TS) {
-    const int nb = (j->n_spk - l) < B_TS ? (int)(j->n_spk - l) : B_TS;  // the last batch may be short
-    for (int k = 0; k < nb; ++k) lcid[k] = q->row[j->src[l + k]];
-    for (int k = 0; k < nb; ++k) {
-      const uint32_t s = j->src[l + k];
-      ts_size[k] = q->row[s + 1] - q->row[s];
-      base[k] = (int)((j->t0 + j->lag[l + k]) % L);
+  int64_t at = 0;
+  while (at < j->n_spk) {
+    spike_batch sb;
+    sb.n = 0;
+    for (; sb.n < j->b_ts && at < j->n_spk; ++sb.n, ++at) {
+      const uint32_t s = j->src[at];
+      sb.first[sb.n] = q->row[s];
+      sb.len[sb.n] = q->row[s + 1] - q->row[s];
+      sb.ring_base[sb.n] = (int)((j->t0 + j->lag[at]) % L);
+      ev += sb.len[sb.n];
     }
-    for (int k = 0; k < nb; ++k) {
-      for (int64_t c = 0; c < ts_size[k]; ++c) {
-        const int64_t e = lcid[k]++;
-        int slot = base[k] + q->dly[e];
-        if (slot >= L) slot -= L;
-        cell[i] = &q->rb[(int64_t)q->tgt[e] * S + slot];
-        wv[i] = q->w[e];
-        if (++i == B_RB) {
-          for (int r = 0; r < B_RB; ++r) __builtin_prefetch(cell[r], 1, 3);
-          for (int r = 0; r < B_RB; ++r) *cell[r] += wv[r];
-          i = 0;
-        }
-      }
-      ev += ts_size[k];
+    flat_cursor fc = {&sb, 0, sb.n ? sb.first[0] : 0};
+    int64_t e;
+    int rb0;
+    while (flat_next(&fc, &e, &rb0)) {
+      int slot = rb0 + q->dly[e];
+      if (slot >= L) slot -= L;
+      stage_put(&st, &q->rb[(int64_t)q->tgt[e] * S + slot], q->w[e]);
     }
   }
-  for (int r = 0; r < i; ++r) *cell[r] += wv[r];  // the staged remainder
+  stage_flush(&st, 0);  /* pairs still staged at the end */
   return ev;
 }
 
