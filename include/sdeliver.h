@@ -61,9 +61,12 @@ typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
  *                    (delay - d_min) * block_neurons + offset in block
  *                    (high half) in one 32-bit word             (4 B);
  *                    needs (d_max - d_min + 1) * block_neurons <= 65536
- * In the source-major layout a record is a u32 {target (26 bits), delay -
- * d_min (6 bits)} plus the weight: f32 (FP32 form, 8 B) or the u16 BF16 /
- * residual bits (the BF16 forms; packed = residual there, 6 B). */
+ * In the source-major layout the targets are cut into parts of 2^tbits
+ * (tbits = 24 - the bits of d_max - d_min, at most 4 parts) and each source
+ * has one segment per part.  A record is a u32 {offset in the part (tbits),
+ * delay - d_min, and for the BF16 forms the weight's high byte in bits
+ * 24-31} plus the f32 weight (FP32 form, 8 B) or the weight's low byte (the
+ * BF16 forms; packed = residual there, 5 B). */
 /* Connection-table layout:
  *   SD_LAYOUT_BLOCK   block-major: the synapses from each source into each
  *                     target block of B neurons form one segment; segments
@@ -119,6 +122,21 @@ typedef struct {
                                 block, binning workgroup) region and delivery,
                                 at most 1024; events past it take a slower
                                 exact path (0 = from the expected rate)        */
+  /* Plastic excitatory synapses (Sec. 6: weight updates driven by the
+   * presynaptic spike, computed at delivery, reading the time of the
+   * target's last spike).  At the delivery of a spike of step t_pre, each
+   * excitatory weight w of a synapse with delay d (all of it on the target
+   * side) sees t_last, the target's latest spike with t_last + d <= t_pre,
+   * and its source's previous spike t_prev:
+   *   if t_last + d > t_prev: w = min(w + A+ exp(-(t_last+d-t_prev) h/tau+), w_max)
+   *   then                    w = max(w - A- exp(-(t_pre-t_last-d) h/tau-), 0)
+   * (nothing without a visible target spike); the updated w is delivered.
+   * Needs the FP32 form, the block-major layout, closed loop, d_min <= 16,
+   * d_min + d_max <= 64 and at most one target block per workgroup pass. */
+  int32_t plastic;           /* 0 static, 1 plastic                             */
+  double stdp_tau_plus, stdp_tau_minus;  /* ms                                  */
+  double stdp_a_plus, stdp_a_minus;      /* weight units                        */
+  double stdp_w_max;                     /* upper weight bound                  */
 } sd_config;
 
 typedef struct {

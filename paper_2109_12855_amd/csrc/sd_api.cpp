@@ -234,8 +234,9 @@ struct sd_ctx {
   unsigned long long* row64 = nullptr;   // segment starts per source
   unsigned long long* cursor64 = nullptr;
   unsigned long long* tiles64 = nullptr;
-  uint32_t* tgtd = nullptr;              // target | (delay - d_min) << 26
-  void* wbits = nullptr;                 // weights (u16 bits or f32)
+  uint32_t* tw = nullptr;                // record words (offset | delay | weight high byte)
+  void* wbits = nullptr;                 // weights (u8 low bytes or f32)
+  int32_t tbits = 0, H = 1;              // target parts of 2^tbits, H of them
   void* bins = nullptr;                  // binned records [NB][bin_P][bin_cap]
   uint32_t* bin_cnt = nullptr;           // records per region [NB][bin_P]
   long long* spill = nullptr;            // full regions' events [d_max][N]
@@ -250,6 +251,12 @@ struct sd_ctx {
   int32_t* r = nullptr;
   float* rb = nullptr;
   uint32_t* list[2] = {nullptr, nullptr};
+  // plastic synapses: spike history per neuron, lag mask and previous spike
+  // per list entry (both lists)
+  uint64_t* pmask = nullptr;
+  int32_t* pbefore = nullptr;
+  uint32_t* aux[2] = {nullptr, nullptr};
+  int32_t* prev[2] = {nullptr, nullptr};
   uint32_t* ext_list = nullptr;  // packed external spike list (list_cap entries)
   int32_t* ext_cnt = nullptr;    // its entry count (device)
   // list counters rotate over three words: the open slice's (ci), the next
@@ -373,6 +380,17 @@ sd_status check_config(const sd_config* c, std::string* why) {
   if (c->block_neurons < 0 || (c->block_neurons % 64) != 0) return bad("block_neurons % 64 != 0");
   if (c->w_cv < 0.0) return bad("negative weight CV");
   if (c->layout < SD_LAYOUT_AUTO || c->layout > SD_LAYOUT_SOURCE) return bad("unknown layout");
+  if (c->plastic) {
+    if (c->plastic != 1) return bad("plastic must be 0 or 1");
+    if (c->wform != SD_W_FP32) return bad("plastic synapses need the FP32 form");
+    if (open_loop(*c)) return bad("plastic synapses need a closed-loop network");
+    if (c->layout == SD_LAYOUT_SOURCE) return bad("plastic synapses need the block-major layout");
+    if (c->d_min > 16 || c->d_min + c->d_max > 64)
+      return bad("plastic synapses need d_min <= 16 and d_min + d_max <= 64");
+    if (!(c->stdp_tau_plus > 0.0) || !(c->stdp_tau_minus > 0.0) || c->stdp_a_plus < 0.0 ||
+        c->stdp_a_minus < 0.0 || !(c->stdp_w_max >= 0.0))
+      return bad("plastic synapses need tau+ , tau- > 0, A+, A- >= 0 and w_max >= 0");
+  }
   return SD_OK;
 }
 
@@ -384,10 +402,11 @@ struct Layout {
   int64_t list_cap;
   bool sm = false;  // source-major layout
   int32_t bin_P = 0, bin_cap = 0, bin_U = 0;  // binning (source-major)
+  int32_t tbits = 0, H = 1;                   // source-major target parts
   size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
       off_counters, off_overflow, off_bins, off_bcnt, off_spill, off_sflag, off_ext, off_extcnt,
-      total;
+      off_pmask, off_pbefore, off_aux0, off_aux1, off_prev0, off_prev1, total;
 };
 
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS of one gfx950 workgroup
@@ -419,7 +438,7 @@ sd_status block_major_fits(const sd_config* c, Layout* L, std::string* why) {
     *why = "packed form needs (d_max - d_min + 1) * block_neurons <= 65536";
     return SD_EUNSUPPORTED;
   }
-  if (slice_lds_bytes(L->B, c->d_min, c->d_max) > 160 * 1024) {
+  if (slice_lds_bytes(L->B, c->d_min, c->d_max, c->plastic != 0) > 160 * 1024) {
     *why = "ring window of a block does not fit the 160 KiB LDS; lower block_neurons";
     return SD_EUNSUPPORTED;
   }
@@ -445,13 +464,19 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     L->sm = true;
   } else {
     s = block_major_fits(c, L, why);
-    if (s != SD_OK && c->layout == SD_LAYOUT_BLOCK) return s;
+    if (s != SD_OK && (c->layout == SD_LAYOUT_BLOCK || c->plastic)) return s;
     L->sm = s != SD_OK;
   }
   if (L->sm) {
-    if (L->N >= (1LL << kTgtBits) || L->n_src >= (1LL << 27) || c->d_max - c->d_min >= 64) {
-      *why = "source-major layout holds at most 2^26 targets, 2^27 sources and "
-             "d_max - d_min < 64";
+    // record word: offset in a part of 2^tbits targets, then the delay
+    // offset in dbits (tbits + dbits = 24); H parts cover the targets
+    int dbits = 1;
+    while ((1 << dbits) < c->d_max - c->d_min + 1) ++dbits;
+    L->tbits = kRecWordBits - dbits;
+    L->H = (int32_t)((L->N + (1LL << L->tbits) - 1) >> L->tbits);
+    if (dbits > 8 || L->H > kMaxParts || L->n_src >= (1LL << 27)) {
+      *why = "source-major layout holds at most 2^27 sources, d_max - d_min < 256 and "
+             "4 target parts of 2^(24 - delay bits) targets";
       return SD_EUNSUPPORTED;
     }
     // The events are binned by target block and accumulated in the same LDS
@@ -498,13 +523,17 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
       *why = "too many target blocks for the binning pass's LDS counters";
       return SD_EUNSUPPORTED;
     }
-    L->M = L->n_src + 1;
-    L->rec_bytes = 4;                                  // target | delay
-    L->dly_bytes = c->wform == SD_W_FP32 ? 4 : 2;      // weight (f32 or u16 bits)
+    L->M = L->n_src * L->H + 1;
+    L->rec_bytes = 4;                                  // offset | delay | weight high byte
+    L->dly_bytes = c->wform == SD_W_FP32 ? 4 : 1;      // f32 weight, or the low byte
   } else {
     L->M = L->n_src * L->NB + 1;
     L->rec_bytes = c->wform == SD_W_FP32 ? 8 : 4;
     L->dly_bytes = c->wform == SD_W_BF16_PACKED ? 0 : 1;
+    if (c->plastic && L->B > kSliceThreads) {
+      *why = "plastic synapses need block_neurons <= 1024";
+      return SD_EUNSUPPORTED;
+    }
   }
   L->n_tiles = (L->M + 4095) / 4096;
   L->list_cap = (int64_t)L->NB * L->B * c->d_min;
@@ -548,6 +577,15 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   // external spike lists (sd_deliver_spikes): packed entries and their count
   L->off_ext = take((size_t)L->list_cap * 4);
   L->off_extcnt = take(4);
+  // plastic synapses: per-neuron spike history, per-entry lag mask and
+  // previous spike of both lists
+  const size_t pl = c->plastic ? 1 : 0;
+  L->off_pmask = take(pl * (size_t)L->N * 8);
+  L->off_pbefore = take(pl * (size_t)L->N * 4);
+  L->off_aux0 = take(pl * (size_t)L->list_cap * 4);
+  L->off_aux1 = take(pl * (size_t)L->list_cap * 4);
+  L->off_prev0 = take(pl * (size_t)L->list_cap * 4);
+  L->off_prev1 = take(pl * (size_t)L->list_cap * 4);
   L->total = o;
   sd_sizes& z = L->sz;
   z.n_local = L->N;
@@ -636,6 +674,17 @@ SliceArgs base_args(sd_ctx* c) {
   a.spk_in_count = c->counters + 1;
   a.spk_count = c->counters + 2;
   a.overflow = c->overflow;
+  if (g.plastic) {
+    const double ln2 = std::log(2.0);
+    a.plastic = 1;
+    a.pmask = c->pmask;
+    a.pbefore = c->pbefore;
+    a.stdp_ap = (float)g.stdp_a_plus;
+    a.stdp_am = (float)g.stdp_a_minus;
+    a.stdp_kp = (float)(g.h / (g.stdp_tau_plus * ln2));
+    a.stdp_km = (float)(g.h / (g.stdp_tau_minus * ln2));
+    a.stdp_wmax = (float)g.stdp_w_max;
+  }
   return a;
 }
 
@@ -659,8 +708,10 @@ sd_status bin_events(sd_ctx* c, const uint32_t* in_list, const int32_t* in_cnt, 
   BinArgs a;
   std::memset(&a, 0, sizeof a);
   a.row = c->row64;
-  a.tgtd = c->tgtd;
+  a.tw = c->tw;
   a.wbits = c->wbits;
+  a.tbits = c->tbits;
+  a.H = c->H;
   a.in_list = in_list;
   a.in_cnt = in_cnt;
   a.in_cap = in_cap;
@@ -731,6 +782,8 @@ sd_status set_pending_input(sd_ctx* c, SliceArgs& a) {
     a.in_list = c->list[c->cur];
     a.in_cnt = c->cnt3 + c->ci;
     a.in_cap = c->list_cap;
+    a.in_aux = c->aux[c->cur];
+    a.in_prev = c->prev[c->cur];
   }
   return SD_OK;
 }
@@ -807,7 +860,9 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
     c->row64 = (unsigned long long*)(A + L.off_row);
     c->cursor64 = (unsigned long long*)(A + L.off_cursor);
     c->tiles64 = (unsigned long long*)(A + L.off_tiles);
-    c->tgtd = (uint32_t*)(A + L.off_syn);
+    c->tw = (uint32_t*)(A + L.off_syn);
+    c->tbits = L.tbits;
+    c->H = L.H;
     c->wbits = A + L.off_dly;
     c->bins = A + L.off_bins;
     c->bin_cnt = (uint32_t*)(A + L.off_bcnt);
@@ -828,6 +883,14 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->list[1] = (uint32_t*)(A + L.off_list1);
   c->ext_list = (uint32_t*)(A + L.off_ext);
   c->ext_cnt = (int32_t*)(A + L.off_extcnt);
+  if (cfg->plastic) {
+    c->pmask = (uint64_t*)(A + L.off_pmask);
+    c->pbefore = (int32_t*)(A + L.off_pbefore);
+    c->aux[0] = (uint32_t*)(A + L.off_aux0);
+    c->aux[1] = (uint32_t*)(A + L.off_aux1);
+    c->prev[0] = (int32_t*)(A + L.off_prev0);
+    c->prev[1] = (int32_t*)(A + L.off_prev1);
+  }
   c->cnt3 = (int32_t*)(A + L.off_cnt);
   c->rec = (uint2*)(A + L.off_rec);
   c->wtab_e = A + L.off_wte;
@@ -892,6 +955,10 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipMemsetAsync(c->counters, 0, 8 * 8, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->overflow, 0, 4, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->cnt3, 0, 3 * 4, c->stream));
+  if (g.plastic) {  // no spikes yet: empty histories, no earlier spike (-1)
+    HIP_TRY(c, hipMemsetAsync(c->pmask, 0, (size_t)c->N * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->pbefore, 0xff, (size_t)c->N * 4, c->stream));
+  }
   HIP_TRY(c, launch_propagators(c->stream, g.model, g.h, g.tau_m, g.tau_syn, g.c_m, g.i_e,
                                 c->prop64, c->prop32));
   HIP_TRY(c, launch_init_state(c->stream, c->N, g.seed, g.v0_lo, g.v0_hi, c->V, c->y1, c->y2,
@@ -900,7 +967,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipMemcpy(c->prop_h, c->prop32, sizeof c->prop_h, hipMemcpyDeviceToHost));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max);
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max, g.plastic != 0);
   if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);
@@ -973,8 +1040,10 @@ sd_status sd_build_connections(sd_ctx* c) {
   if (c->sm) {
     a.row64 = c->row64;
     a.cursor64 = c->cursor64;
-    a.tgtd = c->tgtd;
+    a.tw = c->tw;
     a.wbits = c->wbits;
+    a.tbits = c->tbits;
+    a.H = c->H;
     HIP_TRY(c, hipMemsetAsync(c->row64, 0, (size_t)c->M * 8, c->stream));
     if (c->K > 0) HIP_TRY(c, launch_count_sm(c->stream, a));
     HIP_TRY(c, launch_scan64(c->stream, c->row64, c->M, c->tiles64, c->n_tiles));
@@ -1011,6 +1080,7 @@ sd_status sd_build_connections(sd_ctx* c) {
 
 sd_status sd_set_count_mode(sd_ctx* c, int32_t on) {
   if (!c) return SD_EINVAL;
+  if (on && c->cfg.plastic) return fail(c, SD_EUNSUPPORTED, "count mode of a plastic net");
   c->count_mode = on ? 1 : 0;
   return SD_OK;
 }
@@ -1050,6 +1120,8 @@ sd_status sd_update_neurons(sd_ctx* c, int32_t n_steps) {
   a.t_slice0 = c->pend_t0;
   a.out_list = c->list[c->cur];
   a.out_cnt = c->cnt3 + c->ci;
+  a.out_aux = c->aux[c->cur];
+  a.out_prev = c->prev[c->cur];
   sd_status s = launch_slice_checked(c, a);
   if (s != SD_OK) return s;
   c->pend_open = true;
@@ -1107,6 +1179,8 @@ sd_status deliver_impl(sd_ctx* c, bool own, const uint32_t* d_src, const uint8_t
     sd_status s = set_pending_input(c, a);
     if (s != SD_OK) return s;
   } else {
+    if (g.plastic)
+      return fail(c, SD_EUNSUPPORTED, "plastic nets deliver their own spike lists only");
     if (t0 + g.d_min < c->t_now)
       return fail(c, SD_EINVAL, "arrivals at step %lld precede t_now %lld",
                   (long long)(t0 + g.d_min), (long long)c->t_now);
@@ -1170,6 +1244,8 @@ sd_status next_fused_slice(sd_ctx* c, int32_t m, SliceArgs* out) {
   const int cn = (c->ci + 1) % 3;
   a.out_list = c->list[nxt];
   a.out_cnt = c->cnt3 + cn;
+  a.out_aux = c->aux[nxt];
+  a.out_prev = c->prev[nxt];
   a.zero_cnt = c->cnt3 + (cn + 1) % 3;
   if (deliver && c->sm) {
     // source-major: the binning pass is its own launch (issued now), the
@@ -1380,6 +1456,8 @@ extern "C" {
 
 sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
   if (!c || !used) return SD_EINVAL;
+  if (c->cfg.plastic)
+    return fail(c, SD_EUNSUPPORTED, "checkpoints of plastic nets (their weights are state)");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const int32_t L = c->cfg.ring_len;
   int64_t n_pend = 0;
@@ -1427,6 +1505,8 @@ sd_status sd_save_state(sd_ctx* c, void* h_buf, size_t cap, size_t* used) {
 
 sd_status sd_load_state(sd_ctx* c, const void* h_buf, size_t n) {
   if (!c || !h_buf) return SD_EINVAL;
+  if (c->cfg.plastic)
+    return fail(c, SD_EUNSUPPORTED, "checkpoints of plastic nets (their weights are state)");
   if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
   if (n < sizeof(StateHeader)) return fail(c, SD_EINVAL, "state buffer too short");
   StateHeader hd;
@@ -1506,6 +1586,16 @@ sd_status sd_get_pending(sd_ctx* c, uint32_t* h_src, uint8_t* h_lag, int64_t cap
   std::vector<uint32_t> all((size_t)nl);
   if (nl > 0)
     HIP_TRY(c, hipMemcpy(all.data(), c->list[c->cur], (size_t)nl * 4, hipMemcpyDeviceToHost));
+  if (c->cfg.plastic) {  // one entry per neuron with its lags as a mask
+    std::vector<uint32_t> lm((size_t)nl);
+    if (nl > 0)
+      HIP_TRY(c, hipMemcpy(lm.data(), c->aux[c->cur], (size_t)nl * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> ex;
+    for (int64_t i = 0; i < nl; ++i)
+      for (int l = 0; l < 32; ++l)
+        if ((lm[(size_t)i] >> l) & 1u) ex.push_back((all[(size_t)i] & ~31u) | (uint32_t)l);
+    all.swap(ex);
+  }
   // blocks append in any order: sort by (lag, src)
   std::sort(all.begin(), all.end(), [](uint32_t x, uint32_t y) {
     const uint32_t lx = x & 31u, ly = y & 31u;
@@ -1530,33 +1620,38 @@ sd_status sd_export_connections(sd_ctx* c, int64_t* h_row, int32_t* h_tgt, uint8
   if (c->sm) {
     // source-major: segments are contiguous; their order is the fill's, so
     // sort each by (target, delay, weight) for a canonical export
+    // a source's part segments are adjacent: its row starts at part 0
     std::vector<unsigned long long> rp((size_t)c->M);
     HIP_TRY(c, hipMemcpy(rp.data(), c->row64, (size_t)c->M * 8, hipMemcpyDeviceToHost));
-    for (int64_t s = 0; s <= c->n_src; ++s) h_row[s] = (int64_t)rp[(size_t)s];
+    for (int64_t s = 0; s <= c->n_src; ++s) h_row[s] = (int64_t)rp[(size_t)(s * c->H)];
     if (!h_tgt && !h_dly && !h_w) return SD_OK;
     const sd_config& g = c->cfg;
     const bool f32 = g.wform == SD_W_FP32;
     std::vector<uint32_t> td((size_t)c->n_syn);
-    std::vector<uint8_t> wb((size_t)c->n_syn * (f32 ? 4 : 2));
+    std::vector<uint8_t> wb((size_t)c->n_syn * (f32 ? 4 : 1));
     if (c->n_syn) {
-      HIP_TRY(c, hipMemcpy(td.data(), c->tgtd, td.size() * 4, hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy(td.data(), c->tw, td.size() * 4, hipMemcpyDeviceToHost));
       HIP_TRY(c, hipMemcpy(wb.data(), c->wbits, wb.size(), hipMemcpyDeviceToHost));
     }
+    const uint32_t tmask = (1u << c->tbits) - 1u;
+    const uint32_t dmask = (1u << (kRecWordBits - c->tbits)) - 1u;
     struct Ent { int32_t t; uint8_t d; float w; };
     std::vector<Ent> seg;
     for (int64_t s = 0; s < c->n_src; ++s) {
       const float mu = s < c->src_e_end ? c->mu_e : c->mu_i;
       seg.clear();
-      for (int64_t e = h_row[s]; e < h_row[s + 1]; ++e) {
+      for (int32_t part = 0; part < c->H; ++part)
+      for (int64_t e = (int64_t)rp[(size_t)(s * c->H + part)];
+           e < (int64_t)rp[(size_t)(s * c->H + part + 1)]; ++e) {
         Ent x;
-        x.t = (int32_t)(td[(size_t)e] & ((1u << kTgtBits) - 1));
-        x.d = (uint8_t)(g.d_min + (int)(td[(size_t)e] >> kTgtBits));
+        const uint32_t w0 = td[(size_t)e];
+        x.t = (int32_t)(((int64_t)part << c->tbits) | (w0 & tmask));
+        x.d = (uint8_t)(g.d_min + (int)((w0 >> c->tbits) & dmask));
         if (f32) {
           std::memcpy(&x.w, wb.data() + (size_t)e * 4, 4);
         } else {
-          uint16_t h;
-          std::memcpy(&h, wb.data() + (size_t)e * 2, 2);
-          const uint32_t u = (uint32_t)h << 16;
+          const uint32_t h = ((w0 >> kRecWordBits) << 8) | wb[(size_t)e];
+          const uint32_t u = h << 16;
           float d;
           std::memcpy(&d, &u, 4);
           x.w = g.wform == SD_W_BF16 ? d : std::fma(mu, d, mu);
@@ -1747,6 +1842,8 @@ sd_status sd_batch_create(const sd_config* cfgs, int32_t n, void* hip_stream, sd
                    "member " + std::to_string(i) + ": model, weight form, h and d_min must match");
     if (open_loop(ci))
       return bfail(bt, SD_EUNSUPPORTED, "member " + std::to_string(i) + ": open loop");
+    if (ci.plastic)
+      return bfail(bt, SD_EUNSUPPORTED, "member " + std::to_string(i) + ": plastic synapses");
   }
   std::vector<int2> blocks;
   size_t lds = 0;

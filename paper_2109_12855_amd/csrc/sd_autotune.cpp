@@ -50,6 +50,8 @@ uint64_t problem_hash(const sd_config* cfgs, int32_t n, const int32_t* targets, 
   h = fnv(h, targets, sizeof(int32_t) * (size_t)nt);
   const uint32_t rules = 2;  // uniform and balanced candidates
   h = fnv(h, &rules, sizeof rules);
+  const uint32_t graph = n > 1 ? 1u : 0u;  // batches are timed through the captured graph
+  h = fnv(h, &graph, sizeof graph);
   h = fnv(h, &warmup, sizeof warmup);
   h = fnv(h, &slices, sizeof slices);
   return h;
@@ -171,8 +173,10 @@ double time_candidate(const std::vector<sd_config>& cfgs, int32_t warmup, int32_
     sd_destroy(c);
   } else {
     sd_batch* b = nullptr;
+    // batches run their steady-state slices from the captured graph, as the
+    // tuned configuration will (the timed stretch spans several replays)
     bool ok = sd_batch_create(cfgs.data(), (int32_t)cfgs.size(), s, &b) == SD_OK &&
-              sd_batch_build(b) == SD_OK;
+              sd_batch_build(b) == SD_OK && sd_batch_set_graph(b, 1) == SD_OK;
     ok = ok && sd_batch_simulate_steps(b, (int64_t)warmup * d_min) == SD_OK;
     ok = ok && hipEventRecord(e0, s) == hipSuccess;
     ok = ok && sd_batch_simulate_steps(b, (int64_t)slices * d_min) == SD_OK;

@@ -78,6 +78,21 @@ struct SliceArgs {
   int32_t bin_P, bin_cap;
   long long* spill;
   int32_t* spill_flag;
+  // plastic synapses (block-major FP32 form, closed loop): per neuron the
+  // spikes of the last 64 updated steps (bit k: step T - 1 - k, T the first
+  // step not yet updated) and its latest spike before them (-1: none); per
+  // list entry (one per spiking neuron and slice, src << 5) the slice's lag
+  // mask (bit l: a spike at lag l) and the source's spike before the slice
+  int32_t plastic;
+  uint64_t* pmask;
+  int32_t* pbefore;
+  const uint32_t* in_aux;
+  const int32_t* in_prev;
+  uint32_t* out_aux;
+  int32_t* out_prev;
+  float stdp_ap, stdp_am;   // amplitudes A+, A-
+  float stdp_kp, stdp_km;   // h / (tau ln 2): exp(-x h / tau) = exp2(-x k)
+  float stdp_wmax;
   // ring buffer [L][N] (FP32)
   float* rb;
   int64_t rb_hi;           // rows of steps in [., rb_hi) hold valid sums
@@ -107,11 +122,15 @@ struct BuildArgs {
   uint32_t* row;           // (src, block) counts, then exclusive scan (block-major)
   uint32_t* cursor;        // fill cursors (copy of row)
   uint2* seg;              // source-major (start, count) pairs
-  // source-major layout
-  unsigned long long* row64;     // counts, then exclusive scan, per source
+  // source-major layout: one segment per (source, target part), parts of
+  // 2^tbits targets; record word = offset in part | (delay - d_min) << tbits
+  // | weight bits 8-15 << 24 (BF16 forms), plus the weight's low byte (u8) or
+  // the f32 weight
+  unsigned long long* row64;     // counts, then exclusive scan, per (source, part)
   unsigned long long* cursor64;  // fill cursors
-  uint32_t* tgtd;                // target | (delay - d_min) << 26
-  void* wbits;                   // u16 BF16 / residual bits, or f32 weight
+  uint32_t* tw;                  // record words
+  void* wbits;                   // u8 low weight bytes, or f32 weights
+  int32_t tbits, H;
   void* syn;
   uint8_t* syn_dly;
   int32_t wform;
@@ -127,9 +146,10 @@ struct BuildArgs {
 // target block and written as binned records into per-(block, workgroup)
 // regions (record layout at kBinSlotBits).
 struct BinArgs {
-  const unsigned long long* row;  // [n_src + 1] segment starts
-  const uint32_t* tgtd;           // target | (delay - d_min) << kTgtBits
-  const void* wbits;              // u16 BF16 / residual bits, or f32 weight
+  const unsigned long long* row;  // [n_src * H + 1] segment starts per (source, part)
+  const uint32_t* tw;             // offset | (delay - d_min) << tbits | weight bits 8-15 << 24
+  const void* wbits;              // u8 weight bits 0-7, or f32 weight
+  int32_t tbits, H;               // target part = 2^tbits targets, H parts (<= 4)
   const uint32_t* in_list;        // (src << 5 | lag)
   const int32_t* in_cnt;
   int64_t in_cap;
@@ -160,7 +180,10 @@ constexpr int kBinProducers = 256;
 constexpr int kBinMaxCap = 1024;  // records per region (consumer work items <= 1024)
 constexpr int kBinSlice = 256;    // records per consumer work item
 size_t bin_lds_bytes(int NB, int U, bool w8);
-constexpr int kTgtBits = 26;
+// source-major record word: offset in part (tbits) | delay - d_min (dbits),
+// tbits + dbits = 24, the top byte holds the BF16 weight's high byte
+constexpr int kRecWordBits = 24;
+constexpr int kMaxParts = 4;
 
 // launch wrappers (sd_kernels.hip)
 hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,
@@ -181,7 +204,7 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_ma
                         int32_t n_blocks, size_t lds, int wform);
 // one fused slice of a single network, arguments by value
 hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wform);
-size_t slice_lds_bytes(int B, int Dmin, int win_rows);
+size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic = false);
 // add shift to the time fields (t_upd, t_slice0, w_lo, rb_hi) of args[0..n)
 hipError_t launch_shift_args(hipStream_t s, SliceArgs* args, int32_t n, int64_t shift);
 hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a);

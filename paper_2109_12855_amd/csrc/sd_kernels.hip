@@ -352,28 +352,33 @@ __global__ void k_gather_block(const uint2* seg, int64_t n_src, int32_t NB, int3
 // integers, so results do not, and exports sort segments canonically.
 __global__ void __launch_bounds__(256) k_count_sm(BuildArgs a) {
   const int64_t j = blockIdx.x;
+  const int64_t part = j >> a.tbits;
   for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
     const Draw d = draw_synapse(a, j, k);
-    atomicAdd(&a.row64[d.src], 1ull);
+    atomicAdd(&a.row64[(int64_t)d.src * a.H + part], 1ull);
   }
 }
 
 __global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
   const int64_t j = blockIdx.x;
+  const int64_t part = j >> a.tbits;
+  const uint32_t off = (uint32_t)(j - (part << a.tbits));
   for (int32_t k = threadIdx.x; k < a.K; k += blockDim.x) {
     const Draw d = draw_synapse(a, j, k);
-    const unsigned long long pos = atomicAdd(&a.cursor64[d.src], 1ull);
-    a.tgtd[pos] = (uint32_t)j | ((uint32_t)(d.dly - a.d_min) << kTgtBits);
+    const unsigned long long pos = atomicAdd(&a.cursor64[(int64_t)d.src * a.H + part], 1ull);
+    const uint32_t word = off | ((uint32_t)(d.dly - a.d_min) << a.tbits);
     if (a.wform == WF_FP32) {
       float w;
       if (a.fixed) w = d.inh ? a.w_fix_i : a.w_fix_e;
       else w = d.inh ? ((const float*)a.wtab_i)[d.widx] : ((const float*)a.wtab_e)[d.widx];
+      a.tw[pos] = word;
       ((float*)a.wbits)[pos] = w;
     } else {
       uint32_t wb;
       if (a.fixed) wb = d.inh ? a.fix_bits_i : a.fix_bits_e;
       else wb = d.inh ? ((const uint16_t*)a.wtab_i)[d.widx] : ((const uint16_t*)a.wtab_e)[d.widx];
-      ((uint16_t*)a.wbits)[pos] = (uint16_t)wb;
+      a.tw[pos] = word | ((wb >> 8) << kRecWordBits);
+      ((uint8_t*)a.wbits)[pos] = (uint8_t)wb;
     }
   }
 }
@@ -441,27 +446,34 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   const int64_t s_lo = total * p / P, s_hi = total * (p + 1) / P;
   for (int i = tid; i <= NB; i += kBinThreads) cc[i] = make_uint2(0u, 0u);
   unsigned long long ev = 0;
-  const uint32_t tmask = (1u << kTgtBits) - 1u;
+  const int tbits = a.tbits, H = a.H;
+  const uint32_t tmask = (1u << tbits) - 1u;
+  const uint32_t dmask = (1u << (kRecWordBits - tbits)) - 1u;
   const uint32_t region0 = (uint32_t)p * (uint32_t)cap;  // this workgroup's region in a block's area
   const uint32_t area = (uint32_t)P * (uint32_t)cap;     // records per block
 
-  for (int64_t sb = s_lo; sb < s_hi; sb += kBinSpikes) {
-    const int ns = (int)((s_hi - sb) < kBinSpikes ? (s_hi - sb) : kBinSpikes);
-    // (1) every thread resolves one spike into its segment
+  // every spike has H segments, one per target part: the share walks its
+  // spikes' (spike, part) segment entries
+  for (int64_t sb = s_lo * H; sb < s_hi * H; sb += kBinSpikes) {
+    const int ns = (int)((s_hi * H - sb) < kBinSpikes ? (s_hi * H - sb) : kBinSpikes);
+    // (1) every thread resolves one segment entry
     unsigned long long len = 0;
     if (tid < ns) {
-      const uint32_t ent = a.in_list[sb + tid];
+      const int64_t se = sb + tid;
+      const int64_t i = se / H;
+      const uint32_t part = (uint32_t)(se - i * H);
+      const uint32_t ent = a.in_list[i];
       const uint32_t src = ent >> 5;
       const uint32_t lag = ent & 31u;
       unsigned long long l0 = 0;
       if ((int)lag < a.Dmin && (int64_t)src < a.n_src) {
-        l0 = a.row[src];
-        len = a.row[src + 1] - l0;
-      } else {
+        l0 = a.row[(int64_t)src * H + part];
+        len = a.row[(int64_t)src * H + part + 1] - l0;
+      } else if (part == 0) {
         atomicOr(a.overflow, 4);
       }
       lo[tid] = l0;
-      mt[tid] = lag | (((int64_t)src >= a.src_e_end) ? 0x8000u : 0u);
+      mt[tid] = lag | (((int64_t)src >= a.src_e_end) ? 0x8000u : 0u) | (part << 16);
     }
     unsigned long long n_batch;
     const unsigned long long ex = block_excl_scan<unsigned long long>(len, scr64, n_batch);
@@ -521,10 +533,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
             ++sp;
           }
           const unsigned long long e = l0 + (f - p0);
-          tdk[u] = a.tgtd[e];
+          tdk[u] = a.tw[e];
           if constexpr (W8) wbr[u] = ((const uint32_t*)a.wbits)[e];
-          else wbr[u] = ((const uint16_t*)a.wbits)[e];
-          m4[u >> 2] |= ((m & 31u) | ((m >> 10) & 32u)) << ((u & 3) * 8);  // lag | inh << 5
+          else wbr[u] = ((const uint8_t*)a.wbits)[e];
+          // lag | inh << 5 | part << 6
+          m4[u >> 2] |= ((m & 31u) | ((m >> 10) & 32u) | (((m >> 16) & 3u) << 6)) << ((u & 3) * 8);
         }
       }
     };
@@ -553,17 +566,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           rk[u - h] = 0u;
           if constexpr (W8) rec8[u] = 0u;
           if (u < U && fr < n_ev) {
-            const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 63u;
-            const int tgt = (int)(td & tmask);
+            const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 255u;
+            const int tgt = (int)(((m >> 6) << tbits) | (td & tmask));
             // block = tgt / B from an FP32 estimate, corrected by one step
             int blk = (int)((float)tgt * inv_B);
             int off = tgt - blk * Bv;
             if (off < 0) { --blk; off += Bv; }
             if (off >= Bv) { ++blk; off -= Bv; }
-            const int q = (int)(m & 31u) + (int)(td >> kTgtBits);
+            const int q = (int)(m & 31u) + (int)((td >> tbits) & dmask);
             const uint32_t r = (uint32_t)(q * Bv + off) | ((m & 32u) << 10);
             if constexpr (W8) rec8[u] = r;
-            else wbr[u] = r | (wbr[u] << 16);
+            else wbr[u] = r | ((((td >> kRecWordBits) << 8) | wbr[u]) << 16);
             rk[u - h] = __hip_atomic_fetch_add(&cc[blk].x, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
             tdk[u] = (uint32_t)blk << 16;
@@ -755,9 +768,10 @@ __host__ __device__ inline bool staged_in_regs(int B, int Dmin) {
 
 // LDS layout of a slice workgroup (byte offsets, 16-byte aligned pieces)
 struct SliceLds {
-  size_t win, carry, dcnt, mask, thr, scr, desc, meta, total;
+  size_t win, carry, dcnt, mask, thr, scr, desc, meta, pm, pb, lagm, tpv, total;
 };
-__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_rows) {
+__host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_rows,
+                                                     bool plastic = false) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   SliceLds L;
   size_t o = 0;
@@ -771,12 +785,55 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_ro
   // wave's last group reads in bounds without clamping its index
   L.desc = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 8);  // (start in block, count)
   L.meta = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 4);  // lag row, count, population
+  // plastic synapses: the block's post-spike masks and earlier spikes, and
+  // per spike of a chunk its lag mask and its source's previous spike
+  const size_t np = plastic ? 1 : 0;
+  L.pm = o;    o = up(o + np * (size_t)B * 8);
+  L.pb = o;    o = up(o + np * (size_t)B * 4);
+  L.lagm = o;  o = up(o + np * (size_t)(kSliceThreads + kMaxGroup) * 4);
+  L.tpv = o;   o = up(o + np * (size_t)(kSliceThreads + kMaxGroup) * 4);
   L.total = o;
   return L;
 }
 
-size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
-  return slice_lds_layout(B, Dmin, win_rows).total;
+size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic) {
+  return slice_lds_layout(B, Dmin, win_rows, plastic).total;
+}
+
+// Plastic synapses: one excitatory weight w (delay d, target row of the
+// block's post-spike mask pm / earlier spike pb) takes the source's spikes
+// of one slice in lag order (bits of lm; t0 the slice start, tprev the
+// source's spike before it), each updated by the nearest-spike pair rule and
+// then added into the window row of its arrival step.  T is the first step
+// after the masks (the window's first step): bit k of pm is step T - 1 - k.
+// The arrival row of lag l is l + d - Dmin.
+__device__ __forceinline__ float plastic_walk(const SliceArgs& a, float w, int d, uint64_t pm,
+                                              int32_t pb, uint32_t lm, int32_t tprev, int32_t t0,
+                                              int32_t T, int Dmin, int B, int jl, long long* win,
+                                              float m1) {
+  while (lm) {
+    const int l = __ffs(lm) - 1;
+    lm &= lm - 1;
+    const int32_t t_pre = t0 + l;
+    const int32_t c = t_pre - d;          // latest step whose target spike the synapse sees
+    const int k = T - 1 - c;              // in [Dmin, Dmin + Dmax - 1] <= 63
+    const uint64_t mk = pm >> k;
+    const int32_t t_last = mk ? c - (int32_t)__builtin_ctzll(mk) : pb;
+    if (t_last >= 0) {
+      if (tprev >= 0 && t_last + d > tprev) {
+        w += a.stdp_ap * exp2f(-(float)(t_last + d - tprev) * a.stdp_kp);
+        w = fminf(w, a.stdp_wmax);
+      }
+      w -= a.stdp_am * exp2f(-(float)(t_pre - t_last - d) * a.stdp_km);
+      w = fmaxf(w, 0.f);
+    }
+    const int v = (int)(m1 * w);          // conversion truncates toward zero
+    __hip_atomic_fetch_add((unsigned long long*)&win[(l + d - Dmin) * B + jl],
+                           (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    tprev = t_pre;
+  }
+  return w;
 }
 
 // One workgroup's slice for target block b of the network described by a.
@@ -784,7 +841,7 @@ size_t slice_lds_bytes(int B, int Dmin, int win_rows) {
 // layout, k_bin; WF_FP32 for 8-byte records, any other form for 4-byte
 // ones); otherwise they are read from the block-major segments.
 // DYN: how the window rows due later are flushed (see the flush below).
-template <int WF, bool BIN, bool DYN>
+template <int WF, bool BIN, bool DYN, bool PL = false>
 __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tid = threadIdx.x;
@@ -797,7 +854,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   const int Wd = B >> 5;
   const int Dmin = a.Dmin;
 
-  const SliceLds Lo = slice_lds_layout(B, Dmin, a.win_rows);
+  const SliceLds Lo = slice_lds_layout(B, Dmin, a.win_rows, PL);
   long long* win = (long long*)(lds_raw + Lo.win);
   float* carry = (float*)(lds_raw + Lo.carry);
   uint8_t* dcnt = lds_raw + Lo.dcnt;
@@ -810,6 +867,18 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   // back by whole waves as LDS broadcasts
   uint2* desc = (uint2*)(lds_raw + Lo.desc);
   uint32_t* meta = (uint32_t*)(lds_raw + Lo.meta);
+  uint64_t* pm = (uint64_t*)(lds_raw + Lo.pm);
+  int32_t* pb = (int32_t*)(lds_raw + Lo.pb);
+  uint32_t* lagm = (uint32_t*)(lds_raw + Lo.lagm);
+  int32_t* tpv = (int32_t*)(lds_raw + Lo.tpv);
+  if constexpr (PL) {
+    // the block's post-spike history, read by the delivery (visible after
+    // the first chunk's barrier) and advanced by the update
+    for (int i = tid; i < nb; i += kSliceThreads) {
+      pm[i] = a.pmask[j0 + i];
+      pb[i] = a.pbefore[j0 + i];
+    }
+  }
 
   // Loads consumed only after the first wait of the delivery below, so
   // their latency overlaps the ring-row and state loads.  The list count
@@ -1025,6 +1094,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     __shared__ int s_next;  // next unclaimed spike of the chunk
     uint64_t ev = 0;
     int64_t total = 0;
+    int n_in_spk = 0;  // plastic: input spikes (entries carry several)
     for (int64_t c0 = 0;; c0 += kSliceThreads) {
       // (1) every thread resolves one spike into its segment of this block:
       // the list entry (the first chunk's was loaded with the ring rows),
@@ -1046,10 +1116,19 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         if (lag < Dmin && (int64_t)src < a.n_src) sg = a.seg[(int64_t)src * a.NB + b];
         else atomicOr(a.overflow, 4);
         const uint32_t len = sg.y;
-        ev += (uint64_t)len;
         desc[tid] = sg;
         meta[tid] = ((uint32_t)(lag * B) << 7) | (len < 65u ? len : 65u) |
                     (((int64_t)src >= a.src_e_end) ? 0x80000000u : 0u);
+        if constexpr (PL) {
+          // one entry per spiking source and slice: its lags as a mask
+          const uint32_t lm = a.in_aux[i];
+          lagm[tid] = lm;
+          tpv[tid] = a.in_prev[i];
+          ev += (uint64_t)len * (uint64_t)__popc(lm);
+          n_in_spk += __popc(lm);
+        } else {
+          ev += (uint64_t)len;
+        }
       }
       if (c0 == 0 && tid < kMaxThr) thr[tid] = thr_v;
       if (tid == 0) s_next = 0;
@@ -1084,6 +1163,43 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           mt[u] = meta[g0 + u];
           any_long |= (mt[u] & 127u) > 64u;  // unconditional use: no sinking
         }
+        if constexpr (PL) {
+          // plastic: each lane's synapse takes the entry's spikes in lag
+          // order, its weight updated before each add and stored back
+          const int32_t T = (int32_t)w_lo;
+          const int32_t t0s = (int32_t)(w_lo - Dmin);
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            const uint32_t m = __builtin_amdgcn_readfirstlane(mt[u]);
+            const uint32_t lm = __builtin_amdgcn_readfirstlane(lagm[g0 + u]);
+            const int32_t tp0 = __builtin_amdgcn_readfirstlane(tpv[g0 + u]);
+            const uint32_t sx = __builtin_amdgcn_readfirstlane(desc[g0 + u].x);
+            const bool inh = (int32_t)m < 0;
+            const float m1 = inh ? a.wm1_i : a.wm1_e;
+            if ((u < n_here) & (lane < (int)(m & 127u)) & (lane < 64)) {
+              if constexpr (WF == WF_FP32) {
+                float w = __uint_as_float((uint32_t)raw[u].r);
+                const int jl = (int)(raw[u].r >> 32) - (int)j0;
+                const int dd = (int)raw[u].d;
+                if (inh) {
+                  const int v = (int)(m1 * w);
+                  uint32_t lmi = lm;
+                  while (lmi) {
+                    const int l = __ffs(lmi) - 1;
+                    lmi &= lmi - 1;
+                    __hip_atomic_fetch_add((unsigned long long*)&win[(l + dd - Dmin) * B + jl],
+                                           (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                  }
+                } else {
+                  w = plastic_walk(a, w, dd, pm[jl], pb[jl], lm, tp0, t0s, T, Dmin, B, jl, win,
+                                   m1);
+                  ((uint32_t*)a.syn)[2 * (size_t)(sx + (uint32_t)lane)] = __float_as_uint(w);
+                }
+              }
+            }
+          }
+        } else {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
           // the meta word is uniform: population constants and the lag row
@@ -1102,6 +1218,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
+        }  // static synapses
         // segments longer than one wave (rare: a block's share of a source's
         // targets is ~K/NB)
         if (__builtin_amdgcn_readfirstlane((int)any_long)) {
@@ -1114,6 +1231,32 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
               const bool on = lane + e0 < sl;
               const SynRaw<WF> x =
                   syn_fetch<WF>(a.syn, a.syn_dly, on ? d.x + (uint32_t)(e0 + lane) : 0u);
+              if constexpr (PL && WF == WF_FP32) {
+                if (on) {
+                  const uint32_t lm = lagm[g0 + u];
+                  float w = __uint_as_float((uint32_t)x.r);
+                  const int jl = (int)(x.r >> 32) - (int)j0;
+                  const int dd = (int)x.d;
+                  const float m1 = inh ? a.wm1_i : a.wm1_e;
+                  if (inh) {
+                    const int v = (int)(m1 * w);
+                    uint32_t lmi = lm;
+                    while (lmi) {
+                      const int l = __ffs(lmi) - 1;
+                      lmi &= lmi - 1;
+                      __hip_atomic_fetch_add((unsigned long long*)&win[(l + dd - Dmin) * B + jl],
+                                             (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                  } else {
+                    w = plastic_walk(a, w, dd, pm[jl], pb[jl], lm, tpv[g0 + u],
+                                     (int32_t)(w_lo - Dmin), (int32_t)w_lo, Dmin, B, jl, win, m1);
+                    ((uint32_t*)a.syn)[2 * (size_t)(d.x + (uint32_t)(e0 + lane))] =
+                        __float_as_uint(w);
+                  }
+                }
+                continue;
+              }
               if (on) {
                 int slot, v;
                 syn_decode<WF>(x, (int32_t)j0, Dmin, B, inh ? a.wm0_i : a.wm0_e,
@@ -1139,7 +1282,16 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
     if (lane == 0 && ev)
       __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+    if constexpr (PL) {
+      // input spikes of the slice (entries carry several): block 0 counts
+      if (b == 0) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) n_in_spk += __shfl_xor(n_in_spk, d, 64);
+        if (lane == 0 && n_in_spk) atomicAdd(a.spk_in_count, (unsigned long long)n_in_spk);
+      }
+    } else {
+      if (tid == 0 && b == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
+    }
   } else {
     if (tid < kMaxThr) thr[tid] = thr_v;
     __syncthreads();  // thr / zeroing visible
@@ -1226,6 +1378,12 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       const int64_t gn = j0 + n;
       float V, y1 = 0.f, y2 = 0.f;
       int r;
+      uint64_t hm = 0;
+      int32_t hb = -1;
+      if constexpr (PL) {
+        hm = pm[n];
+        hb = pb[n];
+      }
       if (n == tid) {
         V = sV;
         r = sr;
@@ -1300,12 +1458,33 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           y1 = P11 * y1 + insc * (in + drive);
           y2 = y2n;
         }
-        if (V >= v_th) {
+        const bool spk = V >= v_th;
+        if (spk) {
           V = v_reset;
           r = ref_steps;
-          atomicOr(&mask[(lag_upd + s) * Wd + (n >> 5)], 1u << (n & 31));
+        }
+        if constexpr (PL) {
+          // the step leaving the 64-step history becomes the earlier spike
+          if (hm >> 63) hb = (int32_t)(a.t_upd + s) - 64;
+          hm = (hm << 1) | (uint64_t)spk;
+        }
+        {
+          // the step's spikes of this wave's 64 neurons (consecutive, first
+          // lane active whenever any is): one ballot, two mask words
+          const uint64_t bal = __ballot(spk);
+          if (lane == 0) {
+            const int w0 = (n - lane) >> 5;
+            mask[(lag_upd + s) * Wd + w0] = (uint32_t)bal;
+            mask[(lag_upd + s) * Wd + w0 + 1] = (uint32_t)(bal >> 32);
+          }
         }
         }
+      }
+      if constexpr (PL) {
+        pm[n] = hm;
+        pb[n] = hb;
+        a.pmask[gn] = hm;
+        a.pbefore[gn] = hb;
       }
       a.V[gn] = V;
       a.r[gn] = r;
@@ -1323,8 +1502,60 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   if (a.do_deliver && (!split || (DYN && tid < nb))) flush_rows(tid, kSliceThreads);
   __syncthreads();
 
+  // ---- plastic nets: one entry per spiking neuron, when its slice is complete
+  if constexpr (PL) {
+    if (a.n_upd > 0 && a.t_upd + a.n_upd == a.t_slice0 + Dmin) {
+      uint32_t lm = 0;
+      int32_t tprev = -1;
+      if (tid < nb) {
+        // bit k of the history is step t_slice0 + Dmin - 1 - k: lag l is bit
+        // Dmin - 1 - l; older bits give the spike before the slice
+        const uint64_t hm = pm[tid];
+        for (int l = 0; l < Dmin; ++l) lm |= (uint32_t)((hm >> (Dmin - 1 - l)) & 1u) << l;
+        const uint64_t older = hm >> Dmin;
+        tprev = older ? (int32_t)(a.t_slice0 - 1) - (int32_t)__builtin_ctzll(older) : pb[tid];
+      }
+      // entry positions: wave ballot + mbcnt, wave counts scanned in LDS;
+      // neuron order within the block
+      const bool has = lm != 0u;
+      const uint64_t bal = __ballot(has);
+      const int in_wave =
+          (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      __shared__ int s_wc[kSliceThreads / 64 + 1];
+      __shared__ int s_ebase;
+      if (lane == 0) s_wc[wv] = __popcll(bal);
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < nwv; ++i) {
+          const int c = s_wc[i];
+          s_wc[i] = acc;
+          acc += c;
+        }
+        s_ebase = acc ? atomicAdd(a.out_cnt, acc) : 0;
+      }
+      __syncthreads();
+      if (has) {
+        const int64_t pos = (int64_t)s_ebase + s_wc[wv] + in_wave;
+        const int64_t gn = j0 + tid;
+        if (pos < a.out_cap) {
+          a.out_list[pos] = (uint32_t)gn << 5;
+          a.out_aux[pos] = lm;
+          a.out_prev[pos] = tprev;
+        } else {
+          atomicOr(a.overflow, 1);
+        }
+      }
+      __syncthreads();  // s_wc is reused below
+    }
+  }
+
   // ---- compaction: this block's new spikes, (lag, neuron) ordered --------
+  // (plastic nets: their list entries are built above; here the raster and
+  // the spike count only)
   if (a.n_upd > 0) {
+    const int write_list = PL ? 0 : a.write_list;
     const int lag0 = (int)(a.t_upd - a.t_slice0);
     const int nq = a.n_upd * Wd;
     __shared__ int s_base;
@@ -1338,7 +1569,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
       if (tot == 0) continue;
       // one reservation per block in the slice's list (and the raster)
       if (tid == 0) {
-        s_base = a.write_list ? atomicAdd(a.out_cnt, tot) : 0;
+        s_base = write_list ? atomicAdd(a.out_cnt, tot) : 0;
         s_rbase = a.rec ? atomicAdd(a.rec_n, (unsigned long long)tot) : 0ull;
       }
       __syncthreads();
@@ -1352,7 +1583,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
         const int bit = __ffs(m) - 1;
         m &= m - 1;
         const int64_t gn = j0 + nbase + bit;
-        if (a.write_list) {
+        if (write_list) {
           if (base + pos < a.out_cap)
             a.out_list[base + pos] = ((uint32_t)gn << 5) | (uint32_t)lg;
           else
@@ -1414,14 +1645,14 @@ struct SingleArgs {
   SliceArgs a;
   int32_t per_xcd;
 };
-template <int WF, bool BIN, bool DYN>
+template <int WF, bool BIN, bool DYN, bool PL = false>
 __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
   const SingleArgs* p = (const SingleArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   touch_lines(p);
   const int gx = blockIdx.x;
   const int b = (gx & 7) * p->per_xcd + (gx >> 3);
   if (b >= p->a.NB) return;
-  slice_block<WF, BIN, DYN>(p->a, b);
+  slice_block<WF, BIN, DYN, PL>(p->a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1608,6 +1839,10 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_ma
 template <bool DYN>
 void launch_slice1_as(hipStream_t s, const SingleArgs& sa, size_t lds, int wform) {
   const dim3 grid((unsigned)(8 * sa.per_xcd)), block(kSliceThreads);
+  if (sa.a.plastic) {  // plastic synapses: FP32 block-major only
+    hipLaunchKernelGGL((k_slice1<WF_FP32, false, DYN, true>), grid, block, lds, s, sa);
+    return;
+  }
   if (sa.a.bins) {
     // binned records: 8 bytes (FP32 weight) or 4 (BF16 bits)
     if (wform == WF_FP32) hipLaunchKernelGGL((k_slice1<WF_FP32, true, DYN>), grid, block, lds, s, sa);

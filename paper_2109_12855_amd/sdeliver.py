@@ -52,6 +52,10 @@ class sd_config(C.Structure):
         ("record_cap", C.c_int64),
         ("layout", C.c_int32),
         ("bin_cap", C.c_int32),
+        ("plastic", C.c_int32),
+        ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
+        ("stdp_a_plus", C.c_double), ("stdp_a_minus", C.c_double),
+        ("stdp_w_max", C.c_double),
     ]
 
 

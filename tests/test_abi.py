@@ -106,7 +106,7 @@ def test_brain_share_takes_source_major_layout():
     assert s["layout"] == sdeliver.SD_LAYOUT_SOURCE
     assert s["n_syn"] == 1125000 * 11250
     assert s["n_src"] == 10_000_000
-    assert s["bytes_per_synapse"] == 6
+    assert s["bytes_per_synapse"] == 5     # u32 offset|delay|weight high byte + u8
     assert s["arena_bytes"] < 100 * 2**30
     with pytest.raises(sdeliver.SdError) as e:
         sdeliver.query_sizes(W.ALPHA_BRAIN_SHARE, layout=1)
@@ -118,4 +118,4 @@ def test_layout_choice():
     s = sdeliver.query_sizes(W.ALPHA_112K, layout=2)
     assert s["layout"] == sdeliver.SD_LAYOUT_SOURCE
     assert s["bytes_per_synapse"] == 8
-    assert sdeliver.query_sizes(W.ALPHA_112K_BF16, layout=2)["bytes_per_synapse"] == 6
+    assert sdeliver.query_sizes(W.ALPHA_112K_BF16, layout=2)["bytes_per_synapse"] == 5
