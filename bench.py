@@ -1,13 +1,24 @@
 """Benchmark: synaptic events delivered per second on one MI355X.
 
 A step is one slice of the simulation cycle (Sec. 1 / Sec. 2.1 of the
-paper): deliver the completed slice's spikes through the connection table
-into the ring buffers, then update every neuron through the next d_min
-steps with spike compaction -- one fused kernel launch.  The workload is the
-112,500-neuron alpha-current balanced random net at in-degree 11,250
-(1.27e9 synapses), run closed loop in its self-consistent state; both the
-FP32 form (9 B/synapse) and the BF16-residual form (5 B/synapse) are timed,
-the latter is the headline ``value``.
+paper): the slice's spikes are routed through the connection table into the
+ring buffers (Alg. REF result, Sec. 3.2), and every neuron is updated
+through the next d_min steps with spike compaction.
+
+Headline workload: one GPU's share of a brain-scale network -- 1,125,000
+alpha-current neurons at in-degree 11,250 drawn from a virtual population of
+10,000,000 sources firing at 8 Hz (1.27e10 synapses), BF16-residual weights,
+open loop, 1 ms slices.  A slice is two launches on the context's stream
+(the binning pass and the fused accumulate/update kernel); ``value`` is
+synaptic events per second over the timed slices, the roofline fraction is
+algorithmic bytes per slice (5 B per synapse for the BF16 forms) over the
+measured time per slice, against 8 TB/s.
+
+Also reported: the same share in the FP32 form, the 112,500-neuron closed-
+loop net in its four storage forms (timed after an untimed 200 ms settle),
+ring / rate / CV errors against the FP64 oracle, one-step slices, the
+batched 64-network sweep (FP32 and BF16), the FP64 oracle on the host's
+cores, and the paper's CPU delivery algorithms.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,9 +39,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_slice_alpha_112500_bf16_packed_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
+SHARE_TRAFFIC = os.path.join(PROFILES, "alpha_share_1125000_bf16_resid_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_12855_amd", "csrc", f)
                   for f in ("sd_kernels.hip", "sd_internal.h")]
+SETTLE_SLICES = 200          # untimed biological settle of the closed-loop net (200 ms)
+B_SYN = {0: 9, 1: 5, 2: 5, 3: 4}   # algorithmic bytes per synapse of each storage form
 
 
 def kernel_source_hash() -> str:
@@ -41,13 +55,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per slice launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size), or None when the summary is missing or
-    was taken on different kernel sources."""
+def profile_json(path: str):
+    """The ``traffic_json`` line of a committed rocprofv3 summary (HBM bytes
+    per launch from FETCH_SIZE / WRITE_SIZE scaled by a copy of known size,
+    and the L2 hit rate), or None when it is missing or was taken on other
+    kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             text = fh.read()
     except OSError:
         return None
@@ -62,7 +76,7 @@ def measured_traffic():
 
 def copy_probe():
     """A plain elementwise copy (read and write COPY_PROBE_BYTES each): its
-    FETCH_SIZE / WRITE_SIZE counters calibrate the slice kernel's."""
+    FETCH_SIZE / WRITE_SIZE counters calibrate the slice kernels'."""
     import torch
 
     n = COPY_PROBE_BYTES // 4
@@ -79,14 +93,33 @@ def _log(msg: str):
 
 
 def algorithmic_bytes(events: float, spikes: float, n: int, d_min: int, b_syn: int,
-                      s_state: int) -> float:
+                      s_state: int, b_spike: int = 5) -> float:
     """Bytes one slice must move: synapses of every delivered event, one ring
     write and one read per neuron-step, neuron state read + write, and the
     spike list (5 B per entry)."""
-    return events * b_syn + n * d_min * 8 + n * 2 * s_state + spikes * 5
+    return events * b_syn + n * d_min * 8 + n * 2 * s_state + spikes * b_spike
 
 
-def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dict:
+# Plastic synapses (FP32 form): each event reads its 9-byte record and writes
+# its 4-byte weight back; each neuron's state adds a 12-byte spike history;
+# each spike-list entry adds a lag mask and the source's previous spike.
+PLASTIC_B_EVENT, PLASTIC_S_STATE, PLASTIC_B_SPIKE = 13, 16 + 12, 13
+
+
+def _free(obj):
+    import torch
+
+    obj.close()
+    del obj
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def time_net(cfg: dict, steps: int, warmup: int, settle: int = 0, open_loop: bool = False):
+    """Build, run settle + warmup untimed slices, then time ``steps`` slices
+    with HIP events on the context's stream (torch's current stream: nothing
+    else is launched there in the timed region, so the time per slice is the
+    mean over its launches)."""
     import torch
 
     from paper_2109_12855_amd import sdeliver
@@ -97,7 +130,9 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
     t_build = time.time() - t0
     d_min = cfg["d_min"]
     _log(f"{cfg['name']}: built {net.n_syn:.3e} synapses in {t_build:.1f} s")
-    net.simulate_steps(warmup * d_min)
+    if open_loop:
+        net.prepare_input((settle + warmup + steps + 2) * d_min)
+    net.simulate_steps((settle + warmup) * d_min)
     torch.cuda.synchronize()
     s0 = net.stats()
     start = torch.cuda.Event(enable_timing=True)
@@ -108,78 +143,49 @@ def run_form(cfg: dict, steps: int, warmup: int, per_launch: bool = True) -> dic
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     s1 = net.stats()
-    events = s1["events_delivered"] - s0["events_delivered"]
-    spikes = s1["spikes_delivered"] - s0["spikes_delivered"]
+    ev = s1["events_delivered"] - s0["events_delivered"]
+    spk = s1["spikes_delivered"] - s0["spikes_delivered"]
     emitted = s1["spikes_emitted"] - s0["spikes_emitted"]
-    launches = s1["slices"] - s0["slices"]
-    # Every timed step is one fused slice launch and nothing else runs on
-    # the stream (torch's current stream is the context's), so the events
-    # around the timed region give the kernel's average launch duration.
-    k_ms = ms / launches if per_launch and launches > 0 else None
+    slices = s1["slices"] - s0["slices"]
     n = net.n_local
-    b_syn = {0: 9, 1: 5, 2: 5, 3: 4}[cfg["wform"]]
+    b_syn = B_SYN[cfg["wform"]]
     s_state = 16 if cfg["model"] == 1 else 8
-    b_alg = algorithmic_bytes(events / steps, spikes / steps, n, d_min, b_syn, s_state)
-    out = dict(
-        name=cfg["name"], build_s=round(t_build, 2), ms_total=ms, ms_per_step=ms / steps,
-        events_per_s=events / (ms * 1e-3), events_per_step=events / steps,
-        spikes_per_step=spikes / steps, rate_hz=emitted / (n * steps * d_min * cfg["h"] * 1e-3),
-        alg_bytes_per_step=b_alg, alg_gbs=b_alg / (ms / steps * 1e-3) / 1e9,
-    )
-    if k_ms is not None:
-        b_l = algorithmic_bytes(events / launches, spikes / launches, n, d_min, b_syn, s_state)
-        out.update(kernel_ms=k_ms, launches=launches, kernel_alg_bytes=b_l,
-                   kernel_gbs=b_l / (k_ms * 1e-3) / 1e9)
-    net.close()
-    del net
-    torch.cuda.empty_cache()
-    return out
-
-
-def brain_share(slices: int = 100, warmup: int = 20) -> dict:
-    """The one-GPU share of the brain-scale network (1,125,000 alpha
-    neurons, in-degree 11,250 from a 10M virtual population firing at 8 Hz,
-    1.27e10 synapses, residual-BF16 weights, source-major layout): open-loop
-    input precomputed outside the timed region, then timed slices."""
-    import torch
-
-    from paper_2109_12855_amd import sdeliver, workloads
-
-    cfg = dict(workloads.ALPHA_BRAIN_SHARE)
-    d_min = cfg["d_min"]
-    t0 = time.time()
-    net = sdeliver.Net(cfg).build()
-    torch.cuda.synchronize()
-    t_build = time.time() - t0
-    net.prepare_input((warmup + slices + 2) * d_min)
-    net.simulate_steps(warmup * d_min)
-    torch.cuda.synchronize()
-    s0 = net.stats()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    net.simulate_steps(slices * d_min)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
-    s1 = net.stats()
-    events = s1["events_delivered"] - s0["events_delivered"]
-    spikes = s1["spikes_delivered"] - s0["spikes_delivered"]
-    n = net.n_local
-    b_syn = net.sizes["bytes_per_synapse"]
-    b_alg = algorithmic_bytes(events / slices, spikes / slices, n, d_min, b_syn, 16)
-    out = {"workload": "alpha_share_1125000_k11250_open_loop", "synapses": net.n_syn,
-           "layout": "source_major", "bytes_per_synapse": b_syn, "build_s": round(t_build, 2),
-           "slices": slices, "ms_per_slice": ms / slices, "events_per_slice": events / slices,
-           "spikes_per_slice": spikes / slices, "events_per_s": events / (ms * 1e-3),
-           "alg_gbs": b_alg / (ms / slices * 1e-3) / 1e9,
-           "local_rate_hz": (s1["spikes_emitted"] - s0["spikes_emitted"]) /
-                            (n * slices * d_min * cfg["h"] * 1e-3)}
+    b_spk = 5
+    if cfg.get("plastic"):
+        b_syn, s_state, b_spk = PLASTIC_B_EVENT, PLASTIC_S_STATE, PLASTIC_B_SPIKE
+    b_alg = algorithmic_bytes(ev / slices, spk / slices, n, d_min, b_syn, s_state, b_spk)
+    us = ms * 1e3 / slices
+    out = dict(name=cfg["name"], synapses=net.n_syn, build_s=round(t_build, 2),
+               layout="source_major" if net.sizes["layout"] == 2 else "block_major",
+               stored_bytes_per_synapse=net.sizes["bytes_per_synapse"],
+               alg_bytes_per_synapse=b_syn, slices=slices, ms_total=ms, us_per_slice=us,
+               events_per_slice=ev / slices, spikes_in_per_slice=spk / slices,
+               events_per_s=ev / (ms * 1e-3),
+               rate_hz=emitted / (n * steps * d_min * cfg["h"] * 1e-3),
+               alg_bytes_per_slice=b_alg, alg_gbs=b_alg / (us * 1e-6) / 1e9)
     out["roofline_frac"] = out["alg_gbs"] / HBM_PEAK_GBS
-    net.close()
-    del net
-    torch.cuda.empty_cache()
+    _free(net)
     return out
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def share_cfg(wform: int) -> dict:
+    from paper_2109_12855_amd import workloads
+
+    name = {0: "alpha_share_1125000_fp32", 2: "alpha_share_1125000_bf16_resid"}[wform]
+    return dict(workloads.ALPHA_BRAIN_SHARE, wform=wform, name=name)
+
+
+def alpha_forms():
+    from paper_2109_12855_amd import workloads
+
+    base = workloads.ALPHA_112K
+    return {"fp32": dict(base, wform=0, name="alpha_112500_fp32"),
+            "bf16": dict(base, wform=1, name="alpha_112500_bf16"),
+            "bf16_resid": dict(base, wform=2, name="alpha_112500_bf16_resid"),
+            "bf16_packed": dict(base, wform=3, name="alpha_112500_bf16_packed")}
 
 
 def short_delay(slices: int = 5000, warmup: int = 1000) -> dict:
@@ -188,115 +194,230 @@ def short_delay(slices: int = 5000, warmup: int = 1000) -> dict:
     tenth of the spikes -- the per-slice cost dominates."""
     from paper_2109_12855_amd import workloads
 
-    cfg = dict(workloads.ALPHA_112K_SHORT_DELAY)
-    r = run_form(cfg, slices, warmup)
-    return {"workload": "alpha_112500_k11250_dmin_0.1ms", "slice_ms": cfg["h"] * cfg["d_min"],
-            "slices": slices, "us_per_slice": r["kernel_ms"] * 1e3,
-            "events_per_slice": r["events_per_step"], "spikes_per_slice": r["spikes_per_step"],
-            "events_per_s": r["events_per_s"], "alg_gbs": r["kernel_gbs"],
-            "roofline_frac": r["kernel_gbs"] / HBM_PEAK_GBS, "rate_hz": r["rate_hz"]}
+    r = time_net(dict(workloads.ALPHA_112K_SHORT_DELAY), slices, warmup)
+    r["slice_ms"] = 0.1
+    return r
 
 
 def sweep(slices: int = 120, warmup: int = 20) -> dict:
     """The batched sweep: 64 independent delta networks (N 2,000-40,000, K
-    500-5,000, FP32 weights) advanced together, block sizes from the
-    autotuner (timed here, no cache), steady-state slices replayed from the
-    captured graph; aggregate events/s over all members."""
+    500-5,000) advanced together, FP32 and plain-BF16 weights.  Block sizes
+    come from the autotuner (timed here on the FP32 variant, no cache, batch
+    candidates timed through the captured graph) and serve both variants;
+    steady-state slices replay the captured graph.  Aggregate events/s and
+    algorithmic bytes over all members."""
     import torch
 
     from paper_2109_12855_amd import sdeliver, workloads
 
-    cfgs = workloads.sweep_nets(64)
+    cfgs32 = workloads.sweep_nets(64)
     t0 = time.time()
-    bn, tune_us = sdeliver.autotune(cfgs, targets=(8, 16, 32, 64, 128, 256), warmup=10,
+    bn, tune_us = sdeliver.autotune(cfgs32, targets=(8, 16, 32, 64, 128, 256), warmup=10,
                                     slices=20)
     t_tune = time.time() - t0
-    bt = sdeliver.Batch([dict(c, block_neurons=b) for c, b in zip(cfgs, bn)]).build()
-    bt.set_graph(True)
-    d_min = cfgs[0]["d_min"]
-    bt.simulate_steps(warmup * d_min)
-    torch.cuda.synchronize()
-    ev0 = sum(m.stats()["events_delivered"] for m in bt.members)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    bt.simulate_steps(slices * d_min)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
-    ev1 = sum(m.stats()["events_delivered"] for m in bt.members)
-    out = {"workload": "sweep_64_delta_nets", "networks": len(cfgs),
-           "synapses": int(sum(m.n_syn for m in bt.members)), "slice_ms": d_min * cfgs[0]["h"],
-           "tune_s": round(t_tune, 1), "block_neurons_range": [min(bn), max(bn)],
-           "blocks": int(sum(m.sizes["n_blocks"] for m in bt.members)),
-           "slices": slices, "ms_per_slice": ms / slices,
-           "events_per_s": (ev1 - ev0) / (ms * 1e-3), "graph_replays": bt.graph_launches}
-    bt.close()
-    del bt
-    torch.cuda.empty_cache()
+    out = {"workload": "sweep_64_delta_nets", "networks": len(cfgs32), "slice_ms": 1.5,
+           "tune_s": round(t_tune, 1), "block_neurons_range": [min(bn), max(bn)]}
+    for key, wform in (("fp32", 0), ("bf16", 1)):
+        cfgs = workloads.sweep_nets(64, wform=wform)
+        bt = sdeliver.Batch([dict(c, block_neurons=b) for c, b in zip(cfgs, bn)]).build()
+        bt.set_graph(True)
+        d_min = cfgs[0]["d_min"]
+        bt.simulate_steps(warmup * d_min)
+        torch.cuda.synchronize()
+        st0 = [m.stats() for m in bt.members]
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        bt.simulate_steps(slices * d_min)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        st1 = [m.stats() for m in bt.members]
+        ev = sum(y["events_delivered"] - x["events_delivered"] for x, y in zip(st0, st1))
+        b_alg = 0.0
+        for m, x, y, c in zip(bt.members, st0, st1, cfgs):
+            b_alg += algorithmic_bytes((y["events_delivered"] - x["events_delivered"]) / slices,
+                                       (y["spikes_delivered"] - x["spikes_delivered"]) / slices,
+                                       m.n_local, d_min, B_SYN[wform], 8)
+        us = ms * 1e3 / slices
+        out[key] = {"synapses": int(sum(m.n_syn for m in bt.members)),
+                    "blocks": int(sum(m.sizes["n_blocks"] for m in bt.members)),
+                    "slices": slices, "us_per_slice": us, "events_per_s": ev / (ms * 1e-3),
+                    "alg_bytes_per_slice": b_alg, "alg_gbs": b_alg / (us * 1e-6) / 1e9,
+                    "roofline_frac": b_alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                    "graph_replays": bt.graph_launches}
+        _free(bt)
     return out
 
 
-def ring_errors(base: dict, forms: list, n_spikes: int = 900, seed: int = 2021) -> dict:
-    """Ring contents of each BF16 storage form against the FP32 form after
-    delivering the same replay list (one slice's worth of spikes): normwise
-    relative error over all cells, and the largest cell error relative to
-    the largest FP32 cell."""
+# ---------------------------------------------------------------------------
+# errors against the FP64 oracle
+# ---------------------------------------------------------------------------
+def rate_cv(st, idx, n: int, t_lo: int, t_hi: int, h: float):
+    """Population rate (Hz) over steps [t_lo, t_hi) and the mean ISI CV of
+    the neurons with at least 3 spikes there."""
+    m = (st >= t_lo) & (st < t_hi)
+    st, idx = st[m], idx[m]
+    rate = len(st) / (n * (t_hi - t_lo) * h * 1e-3)
+    order = np.lexsort((st, idx))
+    st, idx = st[order], idx[order]
+    starts = np.flatnonzero(np.r_[True, idx[1:] != idx[:-1]])
+    ends = np.r_[starts[1:], len(idx)]
+    cvs = [np.diff(st[a:b]).std() / np.diff(st[a:b]).mean() for a, b in zip(starts, ends)
+           if b - a >= 3]
+    return rate, float(np.mean(cvs)) if cvs else float("nan")
+
+
+def _err_block(got, ref):
+    d = got.astype(np.float64) - ref
+    return {"normwise": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "max_cell_over_max_ref": float(np.abs(d).max() / np.abs(ref).max())}
+
+
+def ring_errors(forms: dict, share: bool = True, n_spikes: int = 900, seed: int = 2021) -> dict:
+    """Ring contents after one delivery against the FP64 oracle holding the
+    FP32 table weights (the exact weights of the network), on target
+    samples: each storage form of the 112,500-neuron net fed one synthetic
+    slice (900 spikes), and the brain-scale share's residual-BF16 form fed
+    its first open-loop input slice."""
     import torch
 
+    import oracle
     from paper_2109_12855_amd import sdeliver, workloads
 
+    out = {"vs": "FP64 oracle, FP32 table weights", "alpha_112500": {}}
+    base = workloads.ALPHA_112K
     n = base["n_exc"] + base["n_inh"]
+    lo, hi = 40_000, 47_168                        # 16 blocks of 448 targets
     src, lag = workloads.replay_spikes(n, n_spikes, base["d_min"], seed=seed)
+    ref = oracle.Net(dict(base, wform=0, tgt_lo=lo, tgt_hi=hi))
+    ref.deliver(src, lag, 0)
+    exact = ref.ring()
     d_src = torch.from_numpy(src.view(np.int32)).cuda()
     d_lag = torch.from_numpy(lag).cuda()
-    rings = {}
-    for name, wf in [("fp32", 0)] + [(f, {"bf16": 1, "bf16_resid": 2, "bf16_packed": 3}[f])
-                                     for f in forms if f != "fp32"]:
-        net = sdeliver.Net(dict(base, wform=wf)).build()
+    for name, cfg in forms.items():
+        net = sdeliver.Net(cfg).build()
         net.deliver(d_src, d_lag, 0)
-        rings[name] = net.ring(base["ring_len"]).astype(np.float64)
-        net.close()
-        del net
-        torch.cuda.empty_cache()
-    ref = rings.pop("fp32")
-    norm = float(np.linalg.norm(ref))
-    out = {}
-    for name, r in rings.items():
-        d = r - ref
-        out[name] = {"normwise": float(np.linalg.norm(d) / norm),
-                     "max_cell_over_max_ref": float(np.abs(d).max() / np.abs(ref).max())}
-    return {"vs": "fp32 form", "spikes": int(len(src)), "forms": out}
+        out["alpha_112500"][name] = _err_block(net.ring()[:, lo:hi], exact)
+        _free(net)
+    out["alpha_112500_sample"] = f"targets [{lo}, {hi}), {len(src)} spikes"
+    if share:
+        cfg = share_cfg(2)
+        net = sdeliver.Net(cfg).build()
+        net.prepare_input(20)
+        net.simulate_steps(10)
+        net.deliver()
+        s_lo, s_hi = 517_000, 519_496
+        got = net.ring(20)[:, s_lo:s_hi]
+        _free(net)
+        osrc, olag = oracle.open_loop_spikes(cfg, 0, 10, cap=1 << 20)
+        ref = oracle.Net(dict(cfg, wform=0, tgt_lo=s_lo, tgt_hi=s_hi))
+        ref.deliver(osrc, olag, 0)
+        rows = [(10 + q) % cfg["ring_len"] for q in range(20)]
+        out["alpha_share_1125000_bf16_resid"] = _err_block(got, ref.ring()[rows])
+        out["alpha_share_sample"] = f"targets [{s_lo}, {s_hi}), {len(osrc)} input spikes"
+    return out
 
 
-def cpu_baseline(cfg: dict, budget_s: float = 12.0, frac: int = 16) -> dict:
-    """The FP64 oracle on the host: delivery + update of a 1/frac target
-    sample of the same network, fed seeded synthetic spike lists at the
-    GPU run's spike count per slice."""
+def rate_cv_errors(forms: dict, t_ms: float = 500.0, threads: int = 16) -> dict:
+    """Population rate and mean ISI CV (after the first 100 ms) of each
+    storage form's closed-loop run of the 112,500-neuron net, against the
+    FP64 oracle with the FP32 table weights, split into target ranges over
+    host threads."""
+    import oracle
+    from paper_2109_12855_amd import sdeliver
+
+    base = forms["fp32"]
+    steps = int(round(t_ms / base["h"]))
+    n = base["n_exc"] + base["n_inh"]
+    t0 = time.time()
+    part = oracle.Partitioned(dict(base, wform=0), 16, threads=threads)
+    ost, oid = part.simulate(steps)
+    part.close()
+    r_o, cv_o = rate_cv(ost, oid, n, 1000, steps, base["h"])
+    out = {"vs": "FP64 oracle, FP32 table weights", "t_ms": t_ms, "window_ms": [100, t_ms],
+           "oracle": {"rate_hz": r_o, "cv": cv_o, "threads": threads,
+                      "wall_s": round(time.time() - t0, 1)}}
+    for name, cfg in forms.items():
+        net = sdeliver.Net(dict(cfg, record_spikes=1)).build()
+        net.simulate_steps(steps)
+        st, idx = net.spikes()
+        _free(net)
+        r_g, cv_g = rate_cv(st, idx, n, 1000, steps, cfg["h"])
+        out[name] = {"rate_hz": r_g, "cv": cv_g, "rate_rel_err": (r_g - r_o) / r_o,
+                     "cv_rel_err": (cv_g - cv_o) / cv_o}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# host baselines
+# ---------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(threads: int, budget_s: float = 10.0, per_thread: int = 4096) -> dict:
+    """The FP64 oracle on the host, on the headline workload: oracles holding
+    ``per_thread`` targets of the brain-scale share each (all 10M sources),
+    fed the same synthetic open-loop-shaped input lists (80,000 (src, lag)
+    pairs per 1 ms slice, drawn outside the timed region), delivering and
+    updating slice after slice.  One thread alone, then ``threads`` threads
+    at once, each with its own target range; synaptic events on the held
+    targets per wall-clock second."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     from paper_2109_12855_amd import workloads
 
-    n = cfg["n_exc"] + cfg["n_inh"]
-    n_t = n // frac
-    t0 = time.time()
-    ref = oracle.Net(cfg, tgt_lo=0, tgt_hi=n_t)
-    _log(f"oracle sample built ({ref.n_syn:.2e} synapses) in {time.time() - t0:.1f} s")
+    cfg = share_cfg(2)
     d_min = cfg["d_min"]
-    spikes_per_slice = int(round(n * 8.0 * d_min * cfg["h"] * 1e-3))
-    events = 0
-    slices = 0
-    t_start = time.perf_counter()
-    while time.perf_counter() - t_start < budget_s:
-        src, lag = workloads.replay_spikes(n, spikes_per_slice, d_min, seed=1000 + slices)
-        _, ne = ref.deliver(src, lag, ref.t_now - d_min if ref.t_now >= d_min else 0)
-        ref.update(d_min)
-        events += ne
-        slices += 1
-    dt = time.perf_counter() - t_start
-    return {"value": events / dt, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_t} of {n} targets (all sources), {slices} slices of "
-                      f"{spikes_per_slice} spikes, FP64 deliver+update, single thread, "
-                      f"{dt:.1f} s"}
+    n_src = cfg["n_src_exc"] + cfg["n_src_inh"]
+    spikes = int(round(n_src * cfg["src_rate_hz"] * d_min * cfg["h"] * 1e-3))
+    lists = [workloads.replay_spikes(n_src, spikes, d_min, seed=900 + k) for k in range(4)]
+    pool = ThreadPoolExecutor(max_workers=threads)
+    t0 = time.time()
+    nets = list(pool.map(lambda i: oracle.Net(cfg, tgt_lo=i * per_thread,
+                                              tgt_hi=(i + 1) * per_thread), range(threads)))
+    _log(f"oracle samples built ({threads} x {per_thread} targets) in {time.time() - t0:.1f} s")
+
+    def run(net, deadline):
+        ev = 0
+        k = 0
+        while time.perf_counter() < deadline:
+            src, lag = lists[k % len(lists)]
+            t_del = net.t_now - d_min if net.t_now >= d_min else 0
+            ev += net.deliver(src, lag, t_del)[1]
+            net.update(d_min, cap=net.n_local * d_min + 1)
+            k += 1
+        return ev, k
+
+    out = {"unit": "synaptic events/s", "kind": "oracle", "cpu": cpu_model()}
+    t = time.perf_counter()
+    ev, k = run(nets[0], t + budget_s)
+    dt1 = time.perf_counter() - t
+    single = {"value": ev / dt1, "cores": 1, "slices": k, "wall_s": round(dt1, 1)}
+    t = time.perf_counter()
+    res = list(pool.map(lambda nt: run(nt, t + budget_s), nets))
+    dtn = time.perf_counter() - t
+    evn = sum(r[0] for r in res)
+    out.update(value=evn / dtn, cores=threads, single_core=single,
+               sample=f"{threads} oracles of {per_thread} of 1,125,000 targets (all 10M sources, "
+                      f"{per_thread * 11250:.2e} synapses each), {spikes} input spikes per 1 ms "
+                      f"slice, FP64 deliver + update, {sum(r[1] for r in res)} slices in "
+                      f"{dtn:.1f} s on {threads} threads; one thread alone: {k} slices in "
+                      f"{dt1:.1f} s",
+               nproc=os.cpu_count())
+    for nt in nets:
+        nt.__del__()
+    pool.shutdown()
+    return out
 
 
 def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
@@ -348,22 +469,31 @@ def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed slices (1 ms each)")
-    ap.add_argument("--warmup", type=int, default=200, help="untimed slices before timing")
+    ap.add_argument("--steps", type=int, default=100, help="timed slices (1 ms each)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-threads", type=int, default=None,
+                    help="threads of the all-cores oracle baseline (default: all, at most 16)")
     ap.add_argument("--no-cpu-paper", action="store_true",
                     help="skip the multithreaded CPU REF / bwTSRB* comparator")
-    ap.add_argument("--forms", default="fp32,bf16_resid,bf16_packed")
-    ap.add_argument("--no-brain-share", action="store_true",
-                    help="skip the 1.27e10-synapse brain-scale share measurement")
+    ap.add_argument("--forms", default="fp32,bf16,bf16_resid,bf16_packed",
+                    help="storage forms of the 112,500-neuron net")
+    ap.add_argument("--no-share-fp32", action="store_true",
+                    help="skip the FP32 form of the brain-scale share")
     ap.add_argument("--no-precision", action="store_true",
-                    help="skip the BF16-vs-FP32 ring error report")
+                    help="skip the ring errors against the FP64 oracle")
+    ap.add_argument("--no-rate-cv", action="store_true",
+                    help="skip the rate / CV errors against the FP64 oracle")
+    ap.add_argument("--no-plastic", action="store_true",
+                    help="skip the plastic-synapse variant of the 112,500-neuron net")
     ap.add_argument("--no-short-delay", action="store_true",
                     help="skip the one-step-slice (d_min = 0.1 ms) workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the autotuned 64-network batched sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the brain-scale share's BF16 form (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -372,26 +502,47 @@ def main():
 
     import torch
 
-    from paper_2109_12855_amd import workloads
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    base = workloads.ALPHA_112K
-    forms = {"fp32": dict(base, wform=0, name="alpha_112500_fp32"),
-             "bf16": dict(base, wform=1, name="alpha_112500_bf16"),
-             "bf16_resid": dict(base, wform=2, name="alpha_112500_bf16_resid"),
-             "bf16_packed": dict(base, wform=3, name="alpha_112500_bf16_packed")}
-    res = {}
-    for f in args.forms.split(","):
-        _log(f"form {f}")
-        res[f] = run_form(forms[f], args.steps, args.warmup)
-        _log(json.dumps(res[f]))
+    if args.headline_only:
+        args.no_cpu = args.no_cpu_paper = args.no_share_fp32 = args.no_precision = True
+        args.no_rate_cv = args.no_short_delay = args.no_sweep = args.no_plastic = True
+        args.forms = ""
+    # headline: the brain-scale share, BF16-residual weights
+    head = time_net(share_cfg(2), args.steps, args.warmup, open_loop=True)
+    _log("brain share bf16_resid: " + json.dumps(head))
     if args.copy_probe:
         copy_probe()
-    share = None
-    if not args.no_brain_share:
-        share = brain_share()
-        _log("brain share: " + json.dumps(share))
+    share = {"bf16_resid": head}
+    if not args.no_share_fp32:
+        share["fp32"] = time_net(share_cfg(0), args.steps, args.warmup, open_loop=True)
+        _log("brain share fp32: " + json.dumps(share["fp32"]))
+        share["bf16_over_fp32_events_per_s"] = head["events_per_s"] / share["fp32"]["events_per_s"]
+    forms_all = alpha_forms()
+    forms = {f: forms_all[f] for f in args.forms.split(",") if f}
+    alpha = {}
+    for f, cfg in forms.items():
+        alpha[f] = time_net(cfg, args.steps, args.warmup, settle=SETTLE_SLICES)
+        _log(f"alpha_112500 {f}: " + json.dumps(alpha[f]))
+    pl = None
+    if not args.no_plastic:
+        from paper_2109_12855_amd import workloads
+
+        pl = time_net(workloads.plastic(forms_all["fp32"]), args.steps, args.warmup,
+                      settle=SETTLE_SLICES)
+        pl["bytes_per_event"] = PLASTIC_B_EVENT
+        if "fp32" in alpha:
+            pl["over_static_fp32_events_per_s"] = pl["events_per_s"] / alpha["fp32"]["events_per_s"]
+        _log("plastic: " + json.dumps(pl))
+    prec = None
+    if not args.no_precision and forms:
+        prec = ring_errors(forms)
+        _log("ring errors: " + json.dumps(prec))
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    rcv = None
+    if not args.no_rate_cv and "fp32" in forms:
+        rcv = rate_cv_errors(forms, threads=threads)
+        _log("rate/cv: " + json.dumps(rcv))
     sd = None
     if not args.no_short_delay:
         sd = short_delay()
@@ -400,27 +551,22 @@ def main():
     if not args.no_sweep:
         sw = sweep()
         _log("sweep: " + json.dumps(sw))
-    prec = None
-    if not args.no_precision:
-        prec = ring_errors(dict(base, name="precision"),
-                           [f for f in args.forms.split(",") if f != "fp32"])
-        _log("precision: " + json.dumps(prec))
-    head_name = next((f for f in ("bf16_packed", "bf16_resid") if f in res), next(iter(res)))
-    head = res[head_name]
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(dict(base, wform=0))
+        cpu = cpu_baseline(threads)
+        _log("cpu baseline: " + json.dumps(cpu))
     cpu_paper = None
     if not args.no_cpu_paper:
         cpu_paper = cpu_paper_algorithms()
         _log("cpu paper algorithms: " + json.dumps(cpu_paper))
-    roof = None
-    if "kernel_ms" in head:
-        tr = measured_traffic() if head_name == "bf16_packed" else None
-        roof = {"bound": "hbm", "achieved": round(head["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": (round(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
-                            if tr else None)}
+    prof = profile_json(SHARE_TRAFFIC)
+    roof = {"bound": "hbm", "achieved": round(head["alg_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["alg_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": (round(prof["fetch_bytes_per_slice"] + prof["write_bytes_per_slice"])
+                        if prof else None),
+            "kernel": "one slice: binning pass + fused accumulate/update kernel",
+            "alg_bytes_per_slice": head["alg_bytes_per_slice"],
+            "l2_hit_rate": prof.get("l2_hit_rate") if prof else None}
     line = {
         "metric": "synaptic events delivered/s",
         "value": head["events_per_s"],
@@ -428,24 +574,26 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": head["us_per_slice"] * 1e-3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "alpha_112500_k11250_closed_loop", "neurons": 112500,
-                   "in_degree": 11250, "synapses": 112500 * 11250, "slice_ms": 1.0,
-                   "weight_storage": head_name,
+        "config": {"workload": "alpha_share_1125000_k11250_open_loop", "neurons": 1125000,
+                   "in_degree": 11250, "virtual_sources": 10_000_000, "source_rate_hz": 8.0,
+                   "synapses": head["synapses"], "slice_ms": 1.0,
+                   "weight_storage": "bf16_resid", "layout": head["layout"],
                    "parallelism": "single_gpu"},
-        "achieved_alg_gbs": head["alg_gbs"],
-        "forms": res,
-        "precision": prec,
-        "brain_share": share,
-        "short_delay": sd,
-        "sweep": sw,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "brain_share": share,
+        "alpha_112500": alpha,
+        "plastic": pl,
+        "ring_errors": prec,
+        "rate_cv_errors": rcv,
+        "short_delay": sd,
+        "sweep": sw,
         "cpu_paper_algorithms": cpu_paper,
     }
     print(json.dumps(line), flush=True)
