@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
 PROFILES = os.path.join(ROOT, "profiles")
-SHARE_TRAFFIC = os.path.join(PROFILES, "alpha_share_1125000_bf16_resid_traffic.md")
+SHARE_TRAFFIC = os.path.join(PROFILES, "k_bin_k_slice1_alpha_share_1125000_bf16_resid.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_12855_amd", "csrc", f)
                   for f in ("sd_kernels.hip", "sd_internal.h")]
 SETTLE_SLICES = 200          # untimed biological settle of the closed-loop net (200 ms)

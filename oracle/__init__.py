@@ -427,6 +427,12 @@ class Partitioned:
         sts = [p.state() for p in self.parts]
         return {k: np.concatenate([s[k] for s in sts]) for k in sts[0]}
 
+    def set_state(self, V=None, y1=None, y2=None, r=None):
+        """Overwrite the held neurons' state (arrays over [lo, hi))."""
+        off = self.bounds - self.lo
+        for p, a, b in zip(self.parts, off[:-1], off[1:]):
+            p.set_state(*[None if x is None else np.asarray(x)[a:b] for x in (V, y1, y2, r)])
+
     def ring(self):
         return np.concatenate([p.ring() for p in self.parts], axis=1)
 

@@ -174,7 +174,7 @@ struct BinArgs {
 constexpr int kBinSlotBits = 15;
 constexpr int kBinThreads = 1024;
 constexpr int kBinSpikes = 512;   // spikes resolved per descriptor batch
-constexpr int kBinMaxU = 16;      // events per thread per sorting chunk (4-byte records)
+constexpr int kBinMaxU = 12;      // events per thread per sorting chunk (4-byte records; 16 spills)
 constexpr int kBinMaxU8 = 12;     // the same for 8-byte records
 constexpr int kBinProducers = 256;
 constexpr int kBinMaxCap = 1024;  // records per region (consumer work items <= 1024)

@@ -114,3 +114,29 @@ def spike_exact(cfg: dict, gpu, ref_factory, horizon: int, min_exact: int, safet
             return eps, t, n_cmp, ref
         n_cmp += len(a)
     return eps, None, n_cmp, ref
+
+
+# --------------------------------------------------------------------------
+# realization ensembles of chaotic runs
+# --------------------------------------------------------------------------
+def kicked(V, r: int, seed: int = 1):
+    """Initial V of realization ``r`` of a chaotic run: realization 0 is the
+    seeded initial state; realization r > 0 raises 20 neurons' V by 5 mV,
+    which moves some of their first spikes and, through the recurrent
+    chaos, the whole raster within a few hundred ms (a kick of a single
+    neuron can die out before it moves a spike)."""
+    V = np.array(V, copy=True)
+    if r:
+        idx = np.random.default_rng([seed, r]).choice(len(V), 20, replace=False)
+        V[idx] += 5.0
+    return V
+
+
+def realization_z(a, b) -> float:
+    """|mean(a) - mean(b)| in standard errors, with the pooled sample sd of
+    the two realization samples (b may hold a single value)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    ss = ((a - a.mean()) ** 2).sum() + ((b - b.mean()) ** 2).sum()
+    s = np.sqrt(ss / (len(a) + len(b) - 2))
+    return float(abs(a.mean() - b.mean()) / (s * np.sqrt(1.0 / len(a) + 1.0 / len(b))))

@@ -168,3 +168,25 @@ def test_partitioned_open_loop_target_subset():
     part.close()
     with pytest.raises(ValueError):
         oracle.Partitioned(W.tiny(model=0, n=40, k=8), 2, targets=20)
+
+
+def test_partitioned_set_state_and_kicked_realizations():
+    """The partitioned oracle's set_state splits the arrays over its ranges
+    (a kicked start gives the single oracle's kicked run), and a kicked
+    start is a different realization of the same net."""
+    from helpers import kicked
+
+    cfg = W.tiny(model=0, n=200, k=40, seed=12, d_lo=4, d_hi=9)
+    one = oracle.Net(cfg)
+    V = kicked(one.state()["V"], 3)
+    assert (V != one.state()["V"]).sum() == 20
+    one.set_state(V=V)
+    st, idx = one.simulate(400)
+    part = oracle.Partitioned(cfg, 4, threads=2)
+    part.set_state(V=V)
+    pst, pid = part.simulate(400)
+    part.close()
+    assert np.array_equal(pst, st) and np.array_equal(pid, idx)
+    st0, idx0 = oracle.Net(cfg).simulate(400)
+    assert len(st0) > 100
+    assert not (np.array_equal(st0, st) and np.array_equal(idx0, idx))
