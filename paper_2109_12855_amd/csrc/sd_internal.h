@@ -175,10 +175,11 @@ constexpr int kBinSlotBits = 15;
 constexpr int kBinThreads = 1024;
 constexpr int kBinSpikes = 512;   // spikes resolved per descriptor batch
 constexpr int kBinMaxU = 12;      // events per thread per sorting chunk (4-byte records; 16 spills)
-constexpr int kBinMaxU8 = 12;     // the same for 8-byte records
+constexpr int kBinMaxU8 = 8;      // the same for 8-byte records (12 spill)
 constexpr int kBinProducers = 256;
 constexpr int kBinMaxCap = 1024;  // records per region (consumer work items <= 1024)
 constexpr int kBinSlice = 256;    // records per consumer work item
+constexpr int kBinGrp = 4;        // binning: LDS reads issued before one wait (divides kBinMaxU)
 size_t bin_lds_bytes(int NB, int U, bool w8);
 // source-major record word: offset in part (tbits) | delay - d_min (dbits),
 // tbits + dbits = 24, the top byte holds the BF16 weight's high byte

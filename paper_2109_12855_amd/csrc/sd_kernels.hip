@@ -605,50 +605,85 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       __syncthreads();
       // (4) scatter into bin order, with each record's destination: its
       // index in the bin area (block * P * cap + this region's start +
-      // fill + rank), or kNoDst | block when the region is full
+      // fill + rank), or kNoDst | block when the region is full.  The bins'
+      // (start, fill) words of kBinGrp events are read before the first is
+      // used (one LDS wait per group, not one per event).
       constexpr uint32_t kNoDst = 0x80000000u;
 #pragma unroll
-      for (int u = 0; u < UM; ++u) {
-        if (tdk[u] != 0xffffffffu) {
-          const uint32_t blk = tdk[u] >> 16;
-          const uint2 c = cc[blk];
-          const uint32_t at = c.x + (tdk[u] & 0xffffu);
-          const uint32_t pos = c.y + (tdk[u] & 0xffffu);
-          const uint32_t d = pos < (uint32_t)cap ? blk * area + region0 + pos : kNoDst | blk;
-          if constexpr (W8) {
-            stage2[at] = make_uint2(rec8[u], wbr[u]);
-            dst[at] = d;
-          } else {
-            stage2[at] = make_uint2(wbr[u], d);
+      for (int h = 0; h < UM; h += kBinGrp) {
+        uint2 cw[kBinGrp];
+#pragma unroll
+        for (int u = h; u < h + kBinGrp; ++u)
+          cw[u - h] = cc[tdk[u] != 0xffffffffu ? tdk[u] >> 16 : 0u];
+#pragma unroll
+        for (int u = h; u < h + kBinGrp; ++u) {
+          if (tdk[u] != 0xffffffffu) {
+            const uint32_t blk = tdk[u] >> 16;
+            const uint32_t at = cw[u - h].x + (tdk[u] & 0xffffu);
+            const uint32_t pos = cw[u - h].y + (tdk[u] & 0xffffu);
+            const uint32_t d = pos < (uint32_t)cap ? blk * area + region0 + pos : kNoDst | blk;
+            if constexpr (W8) {
+              stage2[at] = make_uint2(rec8[u], wbr[u]);
+              dst[at] = d;
+            } else {
+              stage2[at] = make_uint2(wbr[u], d);
+            }
           }
         }
       }
       __syncthreads();
       // (5) every thread stores sorted records f, f + 1024, ...: a bin's run
-      // goes to consecutive addresses (coalesced stores of ~E_c / NB
-      // records), then the fills advance
+      // goes to consecutive addresses (coalesced stores of ~U * 1024 / NB
+      // records), then the fills advance.  Sorted entries are read kBinGrp
+      // at a time (one LDS wait per group); the bin area's address is held
+      // in registers (read through the argument pointer inside the loop it
+      // would be reloaded, and waited for, before every store, since the
+      // stores might alias it); events of full regions are added in a
+      // separate, rarely taken pass.
       const uint32_t n_chunk = cc[NB].x;
+      {
+        void* const bins = a.bins;
+        bool spill = false;
 #pragma unroll
-      for (int u = 0; u < UM; ++u) {
-        const uint32_t i = (uint32_t)(u * kBinThreads + tid);
-        if (i < n_chunk) {
-          const uint2 x = stage2[i];
-          const uint32_t r = x.x;
-          uint32_t d, wx = 0u;
-          if constexpr (W8) {
-            wx = x.y;
-            d = dst[i];
-          } else {
-            d = x.y;
+        for (int h = 0; h < UM; h += kBinGrp) {
+          uint32_t rv[kBinGrp], dv[kBinGrp], xv[kBinGrp];
+#pragma unroll
+          for (int u = h; u < h + kBinGrp; ++u) {
+            const uint32_t ic = (u < U) ? (uint32_t)(u * kBinThreads + tid) : 0u;
+            const uint2 x = stage2[ic];  // entries past U * 1024 do not exist
+            rv[u - h] = x.x;
+            if constexpr (W8) {
+              xv[u - h] = x.y;
+              dv[u - h] = dst[ic];
+            } else {
+              dv[u - h] = x.y;
+            }
           }
-          if (!(d & kNoDst)) {
-            if constexpr (W8) ((uint2*)a.bins)[d] = make_uint2(r, wx);
-            else ((uint32_t*)a.bins)[d] = r;
-          } else {
-            // region full: add the event's fixed-point weight into the
-            // spill rows with a global atomic
+#pragma unroll
+          for (int u = h; u < h + kBinGrp; ++u) {
+            const uint32_t i = (uint32_t)(u * kBinThreads + tid);
+            if (i < n_chunk) {
+              if (!(dv[u - h] & kNoDst)) {
+                if constexpr (W8) ((uint2*)bins)[dv[u - h]] = make_uint2(rv[u - h], xv[u - h]);
+                else ((uint32_t*)bins)[dv[u - h]] = rv[u - h];
+              } else {
+                spill = true;
+              }
+            }
+          }
+        }
+        if (spill) {
+          // region full: add the event's fixed-point weight into the spill
+          // rows with a global atomic
+          for (int u = 0; u < UM; ++u) {
+            const uint32_t i = (uint32_t)(u * kBinThreads + tid);
+            if (i >= n_chunk) continue;
+            const uint2 x = stage2[i];
+            const uint32_t d = W8 ? dst[i] : x.y;
+            if (!(d & kNoDst)) continue;
             const int bk = (int)(d & ~kNoDst);
-            const float w = W8 ? __uint_as_float(wx) : __uint_as_float(r & 0xffff0000u);
+            const uint32_t r = x.x;
+            const float w = W8 ? __uint_as_float(x.y) : __uint_as_float(r & 0xffff0000u);
             const int slot = (int)(r & ((1u << kBinSlotBits) - 1u));
             const int q = slot / B, off = slot - q * B;
             const bool inh = (r & 0x8000u) != 0u;
