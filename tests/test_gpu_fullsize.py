@@ -13,8 +13,9 @@
   then rate and CV of an ensemble of GPU realizations against the oracle's
   (a two-sample test: past the first rounding-level tie the two runs are
   different realizations of a chaotic network).
-* Two members of the batched sweep (FP32 and BF16 batches): spike-exact over
-  50 ms, then rate and CV over 1 s of GPU and oracle realization ensembles.
+* Two members of the batched sweep (one with FP32, one with BF16 weights):
+  spike-exact over 50 ms, then rate and CV over 1 s of GPU and oracle
+  realization ensembles: means within 2%, and within 4.5 standard errors.
 
 The oracle's Alg. REF result (Sec. 3.2) and grid-exact update (Sec. 2.1)
 define every expected value.
@@ -214,12 +215,15 @@ def test_alpha_112500_rate_cv_vs_oracle(wform, alpha_112500_oracle_run):
 # --------------------------------------------------------------------------
 # batched sweep members
 # --------------------------------------------------------------------------
-# Two members of different size and in-degree (N 28,864 / 25,577, K 1,613 /
-# 3,014).  Their 1 s rates vary by about 2% (sd) between realizations, CVs
-# by about 1%.
-SWEEP_MEMBERS = (0, 4)
-R_SWEEP_GPU = 16
-R_SWEEP_ORACLE = 6
+# One member per weight form, of different size and in-degree: member 0
+# (N 28,864, K 1,613) with FP32 weights and member 4 (N 25,577, K 3,014)
+# with BF16 weights.  Their 1 s rates vary by 1.4-2.6% (sd) between
+# realizations, CVs by 0.8-1.3%.  Each runs as a batch of R_SWEEP_GPU
+# realizations against R_SWEEP_ORACLE[member] oracle realizations, enough
+# that the 2% bound on the ensemble means is >= 3 standard errors of their
+# difference.
+R_SWEEP_GPU = 64
+R_SWEEP_ORACLE = {0: 16, 4: 24}
 
 
 class _Member:
@@ -238,41 +242,42 @@ class _Member:
         return self.m.state()
 
 
-@pytest.mark.parametrize("wform", [0, 1])
-def test_sweep_members_vs_oracle(wform):
-    """Two sweep members (FP32, or BF16 weights), each as a batch of
-    R_SWEEP_GPU realizations: the seeded one spike-exact over 50 ms against
-    the oracle with the same weights, then the ensemble's rate and CV over
-    [100 ms, 1 s) against R_SWEEP_ORACLE oracle realizations."""
-    cfgs = [dict(c, record_spikes=1) for c in W.sweep_nets(64, wform=wform)[:8]]
+@pytest.mark.parametrize("wform,member", [(0, 0), (1, 4)])
+def test_sweep_member_vs_oracle(wform, member):
+    """A sweep member as a batch of R_SWEEP_GPU realizations (the seeded
+    one and kicked ones): the seeded one spike-exact over 50 ms against the
+    oracle with the same weights, then rate and CV over [100 ms, 1 s): the
+    ensemble means within 2% of the oracle ensemble's and within Z_MAX
+    pooled standard errors."""
+    cfg = dict(W.sweep_nets(64, wform=wform)[member], record_spikes=1)
     steps = 10005                     # 667 slices of 1.5 ms
-    for i in SWEEP_MEMBERS:
-        cfg = cfgs[i]
-        n = cfg["n_exc"] + cfg["n_inh"]
-        ocfg = dict(cfg, wform=W.ORACLE_WFORM[wform])
-        bt = sdeliver.Batch([cfg] * R_SWEEP_GPU).build()
-        for r in range(1, R_SWEEP_GPU):
-            m = bt.members[r]
-            m.set_state(V=kicked(m.state()["V"], r))
+    n = cfg["n_exc"] + cfg["n_inh"]
+    ocfg = dict(cfg, wform=W.ORACLE_WFORM[wform])
+    bt = sdeliver.Batch([cfg] * R_SWEEP_GPU).build()
+    for r in range(1, R_SWEEP_GPU):
+        m = bt.members[r]
+        m.set_state(V=kicked(m.state()["V"], r))
 
-        def ref():
-            return oracle.Partitioned(ocfg, THREADS, threads=THREADS)
+    def ref():
+        return oracle.Partitioned(ocfg, THREADS, threads=THREADS)
 
-        eps, t_bad, n_cmp, part = spike_exact(cfg, _Member(bt, 0), ref, horizon=495,
-                                              min_exact=45)
-        assert n_cmp > 50, n_cmp
-        bt.simulate_steps(steps - 495)
-        g = [rate_cv(*bt.members[r].spikes(), n, 1000, steps, cfg["h"])
-             for r in range(R_SWEEP_GPU)]
-        bt.close()
-        o = [rate_cv(*part.simulate(steps - 495), n, 1000, steps, cfg["h"])]
-        part.close()
-        for r in range(1, R_SWEEP_ORACLE):
-            p = oracle.Partitioned(ocfg, THREADS, threads=THREADS)
-            p.set_state(V=kicked(p.state()["V"], 100 + r))
-            o.append(rate_cv(*p.simulate(steps), n, 1000, steps, cfg["h"]))
-            p.close()
-        g, o = np.array(g), np.array(o)
-        assert len(np.unique(g[:, 0])) > R_SWEEP_GPU // 2, "kicks did not give distinct realizations"
-        assert realization_z(g[:, 0], o[:, 0]) <= Z_MAX, (i, g[:, 0], o[:, 0])
-        assert realization_z(g[:, 1], o[:, 1]) <= Z_MAX, (i, g[:, 1], o[:, 1])
+    eps, t_bad, n_cmp, part = spike_exact(cfg, _Member(bt, 0), ref, horizon=495, min_exact=45)
+    assert n_cmp > 50, n_cmp
+    assert eps < 1e-3, eps
+    bt.simulate_steps(steps - 495)
+    g = np.array([rate_cv(*bt.members[r].spikes(), n, 1000, steps, cfg["h"])
+                  for r in range(R_SWEEP_GPU)])
+    bt.close()
+    o = [rate_cv(*part.simulate(steps - 495), n, 1000, steps, cfg["h"])]
+    part.close()
+    for r in range(1, R_SWEEP_ORACLE[member]):
+        p = oracle.Partitioned(ocfg, THREADS, threads=THREADS)
+        p.set_state(V=kicked(p.state()["V"], 1000 + r))
+        o.append(rate_cv(*p.simulate(steps), n, 1000, steps, cfg["h"]))
+        p.close()
+    o = np.array(o)
+    assert len(np.unique(g[:, 0])) > R_SWEEP_GPU // 2, "kicks did not give distinct realizations"
+    for k, name in ((0, "rate"), (1, "cv")):
+        gm, om = g[:, k].mean(), o[:, k].mean()
+        assert abs(gm - om) <= 0.02 * om, (name, gm, om)
+        assert realization_z(g[:, k], o[:, k]) <= Z_MAX, (name, g[:, k], o[:, k])
