@@ -157,6 +157,7 @@ def time_net(cfg: dict, steps: int, warmup: int, settle: int = 0, open_loop: boo
     us = ms * 1e3 / slices
     out = dict(name=cfg["name"], synapses=net.n_syn, build_s=round(t_build, 2),
                layout="source_major" if net.sizes["layout"] == 2 else "block_major",
+               block_neurons=net.sizes["block_neurons"], bin_cap=net.sizes["bin_cap"],
                stored_bytes_per_synapse=net.sizes["bytes_per_synapse"],
                alg_bytes_per_synapse=b_syn, slices=slices, ms_total=ms, us_per_slice=us,
                events_per_slice=ev / slices, spikes_in_per_slice=spk / slices,
@@ -176,6 +177,25 @@ def share_cfg(wform: int) -> dict:
 
     name = {0: "alpha_share_1125000_fp32", 2: "alpha_share_1125000_bf16_resid"}[wform]
     return dict(workloads.ALPHA_BRAIN_SHARE, wform=wform, name=name)
+
+
+def share_tuning(targets=(1353, 1465), cap_scales=(1.0, 1.5)) -> dict:
+    """The binning parameters of the brain-scale share picked by the
+    autotuner (sd_autotune_bins: block sizes for the given block counts x
+    region capacities relative to the automatic one, each built and timed
+    over 20 slices).  The headline itself runs the default parameters, the
+    configuration the committed profile covers."""
+    from paper_2109_12855_amd import sdeliver
+
+    cfg = share_cfg(2)
+    t0 = time.time()
+    bn, cap, us = sdeliver.autotune_bins(cfg, targets=targets, cap_scales=cap_scales, warmup=5,
+                                         slices=20)
+    z = sdeliver.query_sizes(cfg)
+    return {"targets": list(targets), "cap_scales": list(cap_scales),
+            "default": {"block_neurons": z["block_neurons"], "bin_cap": z["bin_cap"]},
+            "chosen": {"block_neurons": bn, "bin_cap": cap}, "us_per_slice": us,
+            "tune_s": round(time.time() - t0, 1)}
 
 
 def alpha_forms():
@@ -517,6 +537,8 @@ def main():
                     help="skip the one-step-slice (d_min = 0.1 ms) workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the autotuned 64-network batched sweep")
+    ap.add_argument("--no-share-tuning", action="store_true",
+                    help="skip the binning-parameter autotuning of the brain-scale share")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     ap.add_argument("--headline-only", action="store_true",
@@ -534,6 +556,7 @@ def main():
     if args.headline_only:
         args.no_cpu = args.no_cpu_paper = args.no_share_fp32 = args.no_precision = True
         args.no_rate_cv = args.no_short_delay = args.no_sweep = args.no_plastic = True
+        args.no_share_tuning = True
         args.forms = ""
     # headline: the brain-scale share, BF16-residual weights
     head = time_net(share_cfg(2), args.steps, args.warmup, open_loop=True)
@@ -545,6 +568,9 @@ def main():
         share["fp32"] = time_net(share_cfg(0), args.steps, args.warmup, open_loop=True)
         _log("brain share fp32: " + json.dumps(share["fp32"]))
         share["bf16_over_fp32_events_per_s"] = head["events_per_s"] / share["fp32"]["events_per_s"]
+    if not args.no_share_tuning:
+        share["tuning"] = share_tuning()
+        _log("brain share tuning: " + json.dumps(share["tuning"]))
     forms_all = alpha_forms()
     forms = {f: forms_all[f] for f in args.forms.split(",") if f}
     alpha = {}
@@ -611,6 +637,7 @@ def main():
                    "in_degree": 11250, "virtual_sources": 10_000_000, "source_rate_hz": 8.0,
                    "synapses": head["synapses"], "slice_ms": 1.0,
                    "weight_storage": "bf16_resid", "layout": head["layout"],
+                   "block_neurons": head["block_neurons"], "bin_cap": head["bin_cap"],
                    "parallelism": "single_gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -148,8 +148,11 @@ typedef struct {
   int64_t table_bytes;       /* synapse arrays + segment pointers               */
   int64_t arena_bytes;       /* total device memory of a context                */
   int32_t bytes_per_synapse; /* block-major: 9 (FP32), 5 (BF16, residual), 4
-                                (packed); source-major: 8 (FP32), 6 (BF16s)   */
+                                (packed); source-major: 8 (FP32), 5 (BF16s)   */
   int32_t layout;            /* the layout in use (SD_LAYOUT_BLOCK / _SOURCE)   */
+  int32_t bin_cap;           /* source-major: binned records per region in use
+                                (the configured or automatic bin_cap); 0 for
+                                block-major                                    */
 } sd_sizes;
 
 typedef struct {
@@ -348,6 +351,25 @@ int64_t sd_batch_graph_launches(const sd_batch* b);
 sd_status sd_autotune(const sd_config* cfgs, int32_t n, const int32_t* targets,
                       int32_t n_targets, int32_t warmup, int32_t slices,
                       const char* cache_path, int32_t* h_block_neurons, double* us_per_slice);
+
+/* Binning parameters of one source-major network: the target block size
+ * (the bucket of the binning pass, as above: ceil(N / T) rounded up to 64
+ * and lowered until the layout fits, for each T in targets[0..n_targets))
+ * and the region capacity bin_cap (each factor of cap_scales[0..n_scales)
+ * times the automatic capacity of that block size, rounded up to 64, within
+ * [64, 32768 / ... the limit of sd_config.bin_cap]; a smaller region sends
+ * more events to the slower spill path, a larger one takes more memory).
+ * Every distinct pair is created, built and timed like sd_autotune; the
+ * fastest goes to *block_neurons and *bin_cap, its time per slice (us) to
+ * *us_per_slice (may be NULL).  cache_path as for sd_autotune (the entry
+ * holds both values).  The configuration's own block_neurons and bin_cap
+ * are ignored.  SD_EINVAL: bad arguments, a configuration whose layout is
+ * not source-major, or the cache file could not be written;
+ * SD_EUNSUPPORTED: no candidate ran. */
+sd_status sd_autotune_bins(const sd_config* cfg, const int32_t* targets, int32_t n_targets,
+                           const double* cap_scales, int32_t n_scales, int32_t warmup,
+                           int32_t slices, const char* cache_path, int32_t* block_neurons,
+                           int32_t* bin_cap, double* us_per_slice);
 
 #ifdef __cplusplus
 }

@@ -598,6 +598,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
                   (L->sm ? 0 : L->n_src * L->NB * 8);
   z.arena_bytes = (int64_t)L->total;
   z.layout = L->sm ? SD_LAYOUT_SOURCE : SD_LAYOUT_BLOCK;
+  z.bin_cap = L->sm ? L->bin_cap : 0;
   return SD_OK;
 }
 

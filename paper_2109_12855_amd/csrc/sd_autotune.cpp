@@ -1,4 +1,5 @@
-// sd_autotune.cpp -- block-size autotuner for single networks and batches.
+// sd_autotune.cpp -- block-size autotuner for single networks and batches,
+// and the binning parameters of source-major networks.
 //
 // A client of the C ABI: every candidate is an ordinary context (or batch),
 // created, built and timed with HIP events on a private stream, then
@@ -12,6 +13,11 @@
 // into T blocks (uniform), or member i into T * K_i / mean(K) blocks
 // (balanced: the events per block of a slice grow with the in-degree, and
 // one launch waits for its slowest blocks).
+//
+// A source-major network's binning pass sorts each slice's events into one
+// bucket per target block, in regions of bin_cap records per (block,
+// binning workgroup): sd_autotune_bins times block sizes (the buckets) and
+// region capacities together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +25,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/sdeliver.h"
@@ -84,7 +91,7 @@ std::string read_file(const char* path) {
 }
 
 bool cache_lookup(const std::string& text, const std::string& key, int32_t n,
-                  std::vector<int32_t>* bn, double* us) {
+                  std::vector<int32_t>* bn, double* us, int32_t* bin_cap = nullptr) {
   const size_t at = text.find("\"" + key + "\"");
   if (at == std::string::npos) return false;
   const size_t end = text.find('}', at);
@@ -93,6 +100,11 @@ bool cache_lookup(const std::string& text, const std::string& key, int32_t n,
   if (end == std::string::npos || pu == std::string::npos || pb == std::string::npos || pu > end ||
       pb > end)
     return false;
+  if (bin_cap) {
+    const size_t pc = text.find("\"bin_cap\":", at);
+    if (pc == std::string::npos || pc > end) return false;
+    *bin_cap = (int32_t)std::strtol(text.c_str() + pc + 10, nullptr, 10);
+  }
   *us = std::strtod(text.c_str() + pu + 15, nullptr);
   bn->clear();
   const char* c = text.c_str() + pb + 18;
@@ -108,7 +120,7 @@ bool cache_lookup(const std::string& text, const std::string& key, int32_t n,
 }
 
 bool cache_store(const char* path, const std::string& key, int32_t target, const char* rule,
-                 double us, const std::vector<int32_t>& bn) {
+                 double us, const std::vector<int32_t>& bn, int32_t bin_cap = -1) {
   std::string text = read_file(path);
   const size_t close = text.rfind('}');
   if (text.find('{') == std::string::npos || close == std::string::npos) text = "{\n}\n";
@@ -118,7 +130,9 @@ bool cache_store(const char* path, const std::string& key, int32_t target, const
   std::snprintf(head, sizeof head,
                 "  \"%s\": {\"target\": %d, \"rule\": \"%s\", \"us_per_slice\": %.3f, ",
                 key.c_str(), target, rule, us);
-  std::string entry = std::string(empty ? "" : ",\n") + head + "\"block_neurons\": [";
+  std::string entry = std::string(empty ? "" : ",\n") + head;
+  if (bin_cap >= 0) entry += "\"bin_cap\": " + std::to_string(bin_cap) + ", ";
+  entry += "\"block_neurons\": [";
   for (size_t i = 0; i < bn.size(); ++i) entry += (i ? ", " : "") + std::to_string(bn[i]);
   entry += "]}\n";
   // drop the whitespace before the closing brace, then append the entry
@@ -246,6 +260,76 @@ sd_status sd_autotune(const sd_config* cfgs, int32_t n, const int32_t* targets, 
   std::copy(best.begin(), best.end(), h_block_neurons);
   if (us_per_slice) *us_per_slice = best_us;
   if (cache_path && !cache_store(cache_path, key, best_t, best_rule, best_us, best))
+    return SD_EINVAL;
+  return SD_OK;
+}
+
+sd_status sd_autotune_bins(const sd_config* cfg, const int32_t* targets, int32_t n_targets,
+                           const double* cap_scales, int32_t n_scales, int32_t warmup,
+                           int32_t slices, const char* cache_path, int32_t* block_neurons,
+                           int32_t* bin_cap, double* us_per_slice) {
+  if (!cfg || !targets || n_targets < 1 || !cap_scales || n_scales < 1 || warmup < 0 ||
+      slices < 1 || !block_neurons || !bin_cap)
+    return SD_EINVAL;
+  for (int32_t k = 0; k < n_targets; ++k)
+    if (targets[k] < 1) return SD_EINVAL;
+  for (int32_t k = 0; k < n_scales; ++k)
+    if (!(cap_scales[k] > 0.0) || !(cap_scales[k] < 1e6)) return SD_EINVAL;
+  {
+    sd_config t = *cfg;
+    t.block_neurons = 0;
+    t.bin_cap = 0;
+    sd_sizes z;
+    if (sd_query_sizes(&t, &z) != SD_OK || z.layout != SD_LAYOUT_SOURCE) return SD_EINVAL;
+  }
+  uint64_t h = problem_hash(cfg, 1, targets, n_targets, warmup, slices);
+  h = fnv(h, cap_scales, sizeof(double) * (size_t)n_scales);
+  char hx[17];
+  std::snprintf(hx, sizeof hx, "%016llx", (unsigned long long)h);
+  const std::string key = device_arch() + ":bins:" + hx;
+  std::vector<int32_t> best;
+  double best_us = -1.0;
+  int32_t best_cap = 0;
+  if (cache_path && cache_lookup(read_file(cache_path), key, 1, &best, &best_us, &best_cap)) {
+    *block_neurons = best[0];
+    *bin_cap = best_cap;
+    if (us_per_slice) *us_per_slice = best_us;
+    return SD_OK;
+  }
+  int32_t best_t = 0;
+  std::vector<std::pair<int32_t, int32_t>> tried;
+  for (int32_t k = 0; k < n_targets; ++k) {
+    const int32_t b = block_for(*cfg, targets[k], 1.0, false);
+    if (b <= 0) continue;
+    sd_config cand = *cfg;
+    cand.block_neurons = b;
+    cand.bin_cap = 0;
+    cand.record_spikes = 0;
+    sd_sizes z;
+    if (sd_query_sizes(&cand, &z) != SD_OK || z.layout != SD_LAYOUT_SOURCE) continue;
+    for (int32_t q = 0; q < n_scales; ++q) {
+      int64_t cap = (int64_t)std::ceil(cap_scales[q] * z.bin_cap);
+      cap = std::min<int64_t>(1024, std::max<int64_t>(64, (cap + 63) / 64 * 64));
+      const std::pair<int32_t, int32_t> pr(b, (int32_t)cap);
+      if (std::find(tried.begin(), tried.end(), pr) != tried.end()) continue;
+      tried.push_back(pr);
+      cand.bin_cap = (int32_t)cap;
+      sd_sizes zc;
+      if (sd_query_sizes(&cand, &zc) != SD_OK) continue;
+      const double us = time_candidate(std::vector<sd_config>(1, cand), warmup, slices);
+      if (us > 0.0 && (best_us < 0.0 || us < best_us)) {
+        best_us = us;
+        best.assign(1, b);
+        best_cap = (int32_t)cap;
+        best_t = targets[k];
+      }
+    }
+  }
+  if (best_us < 0.0) return SD_EUNSUPPORTED;
+  *block_neurons = best[0];
+  *bin_cap = best_cap;
+  if (us_per_slice) *us_per_slice = best_us;
+  if (cache_path && !cache_store(cache_path, key, best_t, "bins", best_us, best, best_cap))
     return SD_EINVAL;
   return SD_OK;
 }

@@ -66,6 +66,7 @@ class sd_sizes(C.Structure):
         ("table_bytes", C.c_int64), ("arena_bytes", C.c_int64),
         ("bytes_per_synapse", C.c_int32),
         ("layout", C.c_int32),
+        ("bin_cap", C.c_int32),
     ]
 
 
@@ -87,7 +88,7 @@ EXPORTS = (
     "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
     "sd_batch_size", "sd_batch_member", "sd_batch_build", "sd_batch_simulate_steps",
     "sd_batch_simulate", "sd_batch_set_graph", "sd_batch_graph_launches", "sd_save_state",
-    "sd_load_state", "sd_autotune", "sd_deliver_spikes_noalloc",
+    "sd_load_state", "sd_autotune", "sd_autotune_bins", "sd_deliver_spikes_noalloc",
 )
 
 _lib = None
@@ -142,6 +143,8 @@ def lib():
         "sd_batch_set_graph": ([vp, i32], i32),
         "sd_batch_graph_launches": ([vp], i64),
         "sd_autotune": ([P(sd_config), i32, vp, i32, i32, i32, C.c_char_p, vp, P(dbl)], i32),
+        "sd_autotune_bins": ([P(sd_config), vp, i32, vp, i32, i32, i32, C.c_char_p,
+                              P(C.c_int32), P(C.c_int32), P(dbl)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -493,3 +496,21 @@ def autotune(cfgs, targets=(16, 32, 64, 128, 256), warmup: int = 10, slices: int
     if rc != SD_OK:
         raise SdError(rc, "sd_autotune")
     return [int(x) for x in out], float(us.value)
+
+
+def autotune_bins(cfg: dict, targets=(1024, 1280, 1536), cap_scales=(0.75, 1.0, 1.5),
+                  warmup: int = 5, slices: int = 10, cache: str | None = None):
+    """Block size and region capacity of a source-major network's binning
+    pass, the fastest pair timed on the current device
+    (``sd_autotune_bins``).  Returns (block_neurons, bin_cap, microseconds
+    per slice)."""
+    c = make_config(dict(cfg))
+    tg = np.ascontiguousarray(targets, np.int32)
+    sc = np.ascontiguousarray(cap_scales, np.float64)
+    bn, cap, us = C.c_int32(), C.c_int32(), C.c_double()
+    rc = lib().sd_autotune_bins(C.byref(c), _ptr(tg), len(tg), _ptr(sc), len(sc), int(warmup),
+                                int(slices), cache.encode() if cache else None, C.byref(bn),
+                                C.byref(cap), C.byref(us))
+    if rc != SD_OK:
+        raise SdError(rc, "sd_autotune_bins")
+    return int(bn.value), int(cap.value), float(us.value)

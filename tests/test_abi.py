@@ -119,3 +119,33 @@ def test_layout_choice():
     assert s["layout"] == sdeliver.SD_LAYOUT_SOURCE
     assert s["bytes_per_synapse"] == 8
     assert sdeliver.query_sizes(W.ALPHA_112K_BF16, layout=2)["bytes_per_synapse"] == 5
+
+
+def test_sizes_report_bin_cap():
+    """The region capacity in use: the automatic one follows its stated rule
+    (expected records per (block, binning workgroup) region at the source
+    rate, x1.25 + 6 sd + 64, rounded up to 64), a configured one is kept,
+    and block-major layouts report 0."""
+    import math
+
+    c = W.ALPHA_BRAIN_SHARE
+    s = sdeliver.query_sizes(c)
+    spikes = (c["n_src_exc"] + c["n_src_inh"]) * c["src_rate_hz"] * c["d_min"] * c["h"] * 1e-3
+    e = spikes / 256 * (s["n_syn"] / s["n_src"]) / s["n_blocks"]
+    want = int(math.ceil(1.25 * e + 6 * math.sqrt(e) + 64))
+    assert s["bin_cap"] == (want + 63) // 64 * 64 == 576
+    assert sdeliver.query_sizes(c, bin_cap=320)["bin_cap"] == 320
+    assert sdeliver.query_sizes(W.ALPHA_112K)["bin_cap"] == 0
+
+
+def test_autotune_bins_rejects_bad_arguments():
+    """Argument checks that need no device: a block-major network, empty or
+    non-positive candidate lists."""
+    with pytest.raises(sdeliver.SdError) as e:
+        sdeliver.autotune_bins(W.ALPHA_112K)
+    assert e.value.status == sdeliver.SD_EINVAL
+    for over in (dict(targets=()), dict(cap_scales=()), dict(cap_scales=(1.0, -0.5)),
+                 dict(targets=(0, 8))):
+        with pytest.raises(sdeliver.SdError) as e:
+            sdeliver.autotune_bins(W.ALPHA_BRAIN_SHARE, **over)
+        assert e.value.status == sdeliver.SD_EINVAL
