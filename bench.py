@@ -516,7 +516,8 @@ def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed slices (1 ms each)")
+    ap.add_argument("--steps", type=int, default=500,
+                    help="timed slices (1 ms each; 500 = the share's configured 0.5 s)")
     ap.add_argument("--warmup", type=int, default=20, help="untimed slices before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-threads", type=int, default=None,
