@@ -408,9 +408,9 @@ __host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
   // weight} with the destinations apart (8-byte records)
   L.stage = o; o = up(o + (size_t)U * kBinThreads * 8);
   L.dst = o;   o = up(o + (w8 ? (size_t)U * kBinThreads * 4 : 0));
-  // per block: {count in the chunk, then the bin's start; records in this
-  // workgroup's region so far}
-  L.cc = o;    o = up(o + (size_t)(NB + 1) * 8);
+  // per block, two arrays used by alternate chunks: {count in the chunk,
+  // then the bin's start; records in this workgroup's region before it}
+  L.cc = o;    o = up(o + (size_t)(NB + 1) * 8 * 2);
   L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per spike
   L.lo = o;    o = up(o + (size_t)kBinSpikes * 8);  // segment start per spike
   L.mt = o;    o = up(o + (size_t)kBinSpikes * 4);  // lag | inhibitory << 15
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   const BinLds Lo = bin_lds_layout(NB, U, W8);
   uint2* stage2 = (uint2*)(lds_raw + Lo.stage);
   uint32_t* dst = (uint32_t*)(lds_raw + Lo.dst);
-  uint2* cc = (uint2*)(lds_raw + Lo.cc);
+  uint2* const cc_arr = (uint2*)(lds_raw + Lo.cc);  // [2][NB + 1]
   unsigned long long* pre = (unsigned long long*)(lds_raw + Lo.pre);
   unsigned long long* lo = (unsigned long long*)(lds_raw + Lo.lo);
   uint32_t* mt = (uint32_t*)(lds_raw + Lo.mt);
@@ -444,7 +444,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
   if (total < 0) total = 0;
   const int64_t s_lo = total * p / P, s_hi = total * (p + 1) / P;
-  for (int i = tid; i <= NB; i += kBinThreads) cc[i] = make_uint2(0u, 0u);
+  for (int i = tid; i < 2 * (NB + 1); i += kBinThreads) cc_arr[i] = make_uint2(0u, 0u);
+  int par = 0;  // counter array of the next chunk
   unsigned long long ev = 0;
   const int tbits = a.tbits, H = a.H;
   const uint32_t tmask = (1u << tbits) - 1u;
@@ -545,6 +546,10 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
     for (unsigned long long f0 = 0; f0 < n_batch; f0 += E_c) {
       const unsigned long long left = n_batch - f0;
       const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
+      // this chunk's counters, and the previous chunk's (its starts and the
+      // fills before it; zero before the first chunk)
+      uint2* const cc = cc_arr + (par ? NB + 1 : 0);
+      uint2* const cp = cc_arr + (par ? 0 : NB + 1);
       // classify: tdk[u] becomes the event's key (block << 16 | rank in the
       // block's bin), wbr[u] (4-byte form) or rec8[u] (FP32) its record
       // Eight events at a time: their rank atomics are all issued before
@@ -587,20 +592,30 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           if (tdk[u] != 0xffffffffu) tdk[u] |= rk[u - h];
       }
       __syncthreads();
-      // (3) bin starts: exclusive scan of the counts, in place
+      // (3) bin starts: exclusive scan of the counts, in place.  The same
+      // pass advances the regions' fills by the previous chunk's runs (its
+      // starts' differences) and, once every thread has read them, clears
+      // the previous chunk's counters for the next chunk.
       {
         const int per = (NB + kBinThreads - 1) / kBinThreads;
         const int i0 = tid * per, i1 = (i0 + per) < NB ? i0 + per : NB;
         uint32_t sum = 0;
-        for (int i = i0; i < i1; ++i) sum += cc[i].x;
+        for (int i = i0; i < i1; ++i) {
+          sum += cc[i].x;
+          cc[i].y = cp[i].y + (cp[i + 1].x - cp[i].x);
+        }
         uint32_t n_chunk;
         uint32_t run = block_excl_scan<uint32_t>(sum, scr32, n_chunk);
         for (int i = i0; i < i1; ++i) {
           const uint32_t c = cc[i].x;
           cc[i].x = run;
           run += c;
+          cp[i].x = 0u;
         }
-        if (tid == 0) cc[NB].x = n_chunk;
+        if (tid == 0) {
+          cc[NB].x = n_chunk;
+          cp[NB].x = 0u;
+        }
       }
       __syncthreads();
       // (4) scatter into bin order, with each record's destination: its
@@ -699,15 +714,21 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       // issued after this chunk's stores: the classify's first wait for a
       // load also waits for every store issued before it.
       if (f0 + E_c < n_batch) issue(f0 + E_c);
-      for (int b = tid; b < NB; b += kBinThreads) cc[b].y += cc[b + 1].x - cc[b].x;
-      __syncthreads();
-      for (int i = tid; i <= NB; i += kBinThreads) cc[i].x = 0u;
-      __syncthreads();
+      // no barrier: the next chunk's counters were cleared before this
+      // chunk's scatter, and its scatter overwrites the stage only after two
+      // more barriers
+      par ^= 1;
     }
   }
-  // record counts of this workgroup's regions
-  for (int b = tid; b < NB; b += kBinThreads)
-    a.bin_cnt[(size_t)b * P + p] = cc[b].y < (uint32_t)cap ? cc[b].y : (uint32_t)cap;
+  // record counts of this workgroup's regions: the last chunk's fills plus
+  // its runs (all zero if there was no chunk)
+  {
+    const uint2* const cl = cc_arr + (par ? 0 : NB + 1);
+    for (int b = tid; b < NB; b += kBinThreads) {
+      const uint32_t f = cl[b].y + (cl[b + 1].x - cl[b].x);
+      a.bin_cnt[(size_t)b * P + p] = f < (uint32_t)cap ? f : (uint32_t)cap;
+    }
+  }
   if (tid == 0) {
     if (ev) atomicAdd(a.ev_count, ev);
     if (p == 0) atomicAdd(a.spk_in_count, (unsigned long long)total);
