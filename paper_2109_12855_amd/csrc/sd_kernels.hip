@@ -185,6 +185,30 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T& total) {
   return res;
 }
 
+// The same scan with one barrier: every thread adds up the wave totals
+// before its own wave.  sh must not be reused before the caller's next
+// barrier.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan1(T v, T* sh, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    const T x = sh[i];
+    before += i < w ? x : (T)0;
+    all += x;
+  }
+  total = all;
+  return inc - v + before;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const T* data, int64_t n,
                                                             T* tile_sums) {
@@ -477,7 +501,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       mt[tid] = lag | (((int64_t)src >= a.src_e_end) ? 0x8000u : 0u) | (part << 16);
     }
     unsigned long long n_batch;
-    const unsigned long long ex = block_excl_scan<unsigned long long>(len, scr64, n_batch);
+    const unsigned long long ex = block_excl_scan1<unsigned long long>(len, scr64, n_batch);
     if (tid < ns) pre[tid] = ex;
     if (tid == 0) pre[ns] = n_batch;
     ev += n_batch;  // the same value in every thread; thread 0 reports it
@@ -605,7 +629,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           cc[i].y = cp[i].y + (cp[i + 1].x - cp[i].x);
         }
         uint32_t n_chunk;
-        uint32_t run = block_excl_scan<uint32_t>(sum, scr32, n_chunk);
+        uint32_t run = block_excl_scan1<uint32_t>(sum, scr32, n_chunk);
         for (int i = i0; i < i1; ++i) {
           const uint32_t c = cc[i].x;
           cc[i].x = run;
