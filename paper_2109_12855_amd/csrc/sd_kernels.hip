@@ -1740,10 +1740,11 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
 // ---------------------------------------------------------------------------
 __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64_t t_hi) {
   const int64_t rows = t_hi - t_lo;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows * N) return;
-  const int64_t t = t_lo + i / N;
-  rb[(t % L) * N + (i % N)] = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows * N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = t_lo + i / N;
+    rb[(t % L) * N + (i % N)] = 0.f;
+  }
 }
 
 // An external spike list (separate source and lag arrays) packed into the
@@ -1775,19 +1776,23 @@ __device__ __forceinline__ uint32_t half32(const uint64_t w[4], int64_t t) {
 }
 
 // spikes of every virtual source over [t0, t0 + n_steps), counted per slice
+// (source, 8-step chunk) items, grid-stride: a schedule of many slices of
+// a brain-scale population has more items than one dispatch's 2^32
+// work-items.
 __global__ void k_input_count(uint64_t seed, int64_t n_src, int64_t t0, int32_t n_steps,
                               int32_t Dmin, uint32_t thr, int32_t* cnt) {
   const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_src * n_chunks) return;
-  const int64_t s = i % n_src;
-  const int64_t c = (t0 >> 3) + i / n_src;
-  uint64_t w[4];
-  philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
-  for (int q = 0; q < 8; ++q) {
-    const int64_t t = c * 8 + q;
-    if (t < t0 || t >= t0 + n_steps) continue;
-    if (half32(w, t) < thr) atomicAdd(&cnt[(t - t0) / Dmin], 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_src * n_chunks;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i % n_src;
+    const int64_t c = (t0 >> 3) + i / n_src;
+    uint64_t w[4];
+    philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
+    for (int q = 0; q < 8; ++q) {
+      const int64_t t = c * 8 + q;
+      if (t < t0 || t >= t0 + n_steps) continue;
+      if (half32(w, t) < thr) atomicAdd(&cnt[(t - t0) / Dmin], 1);
+    }
   }
 }
 
@@ -1795,20 +1800,21 @@ __global__ void k_input_fill(uint64_t seed, int64_t n_src, int64_t t0, int32_t n
                              int32_t Dmin, uint32_t thr, const int64_t* off, int32_t* cursor,
                              uint32_t* list) {
   const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_src * n_chunks) return;
-  const int64_t s = i % n_src;
-  const int64_t c = (t0 >> 3) + i / n_src;
-  uint64_t w[4];
-  philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
-  for (int q = 0; q < 8; ++q) {
-    const int64_t t = c * 8 + q;
-    if (t < t0 || t >= t0 + n_steps) continue;
-    if (half32(w, t) < thr) {
-      const int64_t sl = (t - t0) / Dmin;
-      const int lag = (int)((t - t0) - sl * Dmin);
-      const int p = atomicAdd(&cursor[sl], 1);
-      list[off[sl] + p] = ((uint32_t)s << 5) | (uint32_t)lag;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_src * n_chunks;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i % n_src;
+    const int64_t c = (t0 >> 3) + i / n_src;
+    uint64_t w[4];
+    philox(seed, STREAM_SRC, (uint64_t)s, (uint64_t)c, w);
+    for (int q = 0; q < 8; ++q) {
+      const int64_t t = c * 8 + q;
+      if (t < t0 || t >= t0 + n_steps) continue;
+      if (half32(w, t) < thr) {
+        const int64_t sl = (t - t0) / Dmin;
+        const int lag = (int)((t - t0) - sl * Dmin);
+        const int p = atomicAdd(&cursor[sl], 1);
+        list[off[sl] + p] = ((uint32_t)s << 5) | (uint32_t)lag;
+      }
     }
   }
 }
@@ -1816,6 +1822,13 @@ __global__ void k_input_fill(uint64_t seed, int64_t n_src, int64_t t0, int32_t n
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
+// Workgroups of a grid-stride launch over n items: enough to fill the
+// device, and far below a dispatch's 2^32 work-items.
+unsigned stride_grid(int64_t n, int threads) {
+  const int64_t want = (n + threads - 1) / threads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)1 << 20));
+}
+
 hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,
                               double c_m, double i_e, double* p64, float* p32) {
   hipLaunchKernelGGL(k_propagators, dim3(1), dim3(1), 0, s, model, h, tau_m, tau_syn, c_m, i_e,
@@ -1975,8 +1988,8 @@ hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int6
                             int64_t t_hi) {
   if (t_hi <= t_lo) return hipSuccess;
   const int64_t n = (t_hi - t_lo) * N;
-  hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rb, N, L,
-                     t_lo, t_hi);
+  hipLaunchKernelGGL(k_zero_rows, dim3(stride_grid(n, 256)), dim3(256), 0, s, rb, N, L, t_lo,
+                     t_hi);
   return hipGetLastError();
 }
 
@@ -1994,7 +2007,7 @@ hipError_t launch_input_count(hipStream_t s, uint64_t seed, int64_t n_src, int64
                               int32_t n_steps, int32_t Dmin, uint32_t thr, int32_t* cnt) {
   const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
   const int64_t n = n_src * n_chunks;
-  hipLaunchKernelGGL(k_input_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed,
+  hipLaunchKernelGGL(k_input_count, dim3(stride_grid(n, 256)), dim3(256), 0, s, seed,
                      n_src, t0, n_steps, Dmin, thr, cnt);
   return hipGetLastError();
 }
@@ -2004,7 +2017,7 @@ hipError_t launch_input_fill(hipStream_t s, uint64_t seed, int64_t n_src, int64_
                              int32_t* cursor, uint32_t* list) {
   const int64_t n_chunks = ((t0 + n_steps - 1) >> 3) - (t0 >> 3) + 1;
   const int64_t n = n_src * n_chunks;
-  hipLaunchKernelGGL(k_input_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed,
+  hipLaunchKernelGGL(k_input_fill, dim3(stride_grid(n, 256)), dim3(256), 0, s, seed,
                      n_src, t0, n_steps, Dmin, thr, off, cursor, list);
   return hipGetLastError();
 }

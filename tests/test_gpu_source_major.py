@@ -215,3 +215,21 @@ def test_brain_share_full_size_sample():
     st = net.stats()
     assert st["spikes_delivered"] == len(src)
     assert st["overflow"] == 0
+
+
+def test_long_open_loop_schedule_is_complete():
+    """An input schedule of 523 slices of 10M virtual sources has 6.5e9
+    (source, 8-step chunk) draws, more than one dispatch's 2^32 work-items:
+    the spikes delivered in the last slices equal the oracle's draws for
+    them exactly."""
+    cfg = dict(W.ALPHA_BRAIN_SHARE, n_exc=800, n_inh=200, k_exc=80, k_inh=20)
+    net = sdeliver.Net(cfg).build()
+    net.prepare_input(5230)
+    net.simulate_steps(5000)
+    s0 = net.stats()["spikes_delivered"]
+    net.simulate_steps(30)           # delivers the slices starting at 4990, 5000, 5010
+    got = net.stats()["spikes_delivered"] - s0
+    net.close()
+    src, lag = oracle.open_loop_spikes(cfg, 4990, 30, cap=1 << 21)
+    assert len(src) > 200_000
+    assert got == len(src)
