@@ -544,6 +544,9 @@ def main():
                     help="also run a plain copy of known size (counter calibration)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the brain-scale share's BF16 form (profiling runs)")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="only the 112,500-neuron net's --forms (profiling runs; the JSON line "
+                         "then holds those legs alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -559,6 +562,15 @@ def main():
         args.no_rate_cv = args.no_short_delay = args.no_sweep = args.no_plastic = True
         args.no_share_tuning = True
         args.forms = ""
+    if args.forms_only:
+        forms_all = alpha_forms()
+        alpha = {f: time_net(forms_all[f], args.steps, args.warmup, settle=SETTLE_SLICES)
+                 for f in args.forms.split(",") if f}
+        if args.copy_probe:
+            copy_probe()
+        print(json.dumps({"alpha_112500": alpha, "steps": args.steps, "warmup": args.warmup,
+                          "settle_slices": SETTLE_SLICES}), flush=True)
+        return
     # headline: the brain-scale share, BF16-residual weights
     head = time_net(share_cfg(2), args.steps, args.warmup, open_loop=True)
     _log("brain share bf16_resid: " + json.dumps(head))
