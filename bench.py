@@ -179,7 +179,7 @@ def share_cfg(wform: int) -> dict:
     return dict(workloads.ALPHA_BRAIN_SHARE, wform=wform, name=name)
 
 
-def share_tuning(targets=(1353, 1465), cap_scales=(1.0, 1.5)) -> dict:
+def share_tuning(targets=(1256, 1353), cap_scales=(1.0, 1.5)) -> dict:
     """The binning parameters of the brain-scale share picked by the
     autotuner (sd_autotune_bins: block sizes for the given block counts x
     region capacities relative to the automatic one, each built and timed

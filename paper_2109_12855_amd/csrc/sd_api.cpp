@@ -483,7 +483,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
     // ring windows as the block-major layout: the largest block whose window
     // fits the LDS and whose slots fit the binned record's 15 bits.
     auto fits = [&](int64_t b) {
-      return slice_lds_bytes((int)b, c->d_min, c->d_max) + 64 <= kLdsBudget &&
+      return slice_lds_bytes((int)b, c->d_min, c->d_max, false, true) + 64 <= kLdsBudget &&
              (int64_t)c->d_max * b <= (1 << kBinSlotBits);
     };
     int64_t b = c->block_neurons;
@@ -968,7 +968,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   HIP_TRY(c, hipMemcpy(c->prop_h, c->prop32, sizeof c->prop_h, hipMemcpyDeviceToHost));
   int lds_max = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max, g.plastic != 0);
+  const size_t lds = slice_lds_bytes(c->B, g.d_min, g.d_max, g.plastic != 0, c->sm);
   if ((size_t)lds_max < lds + 64)
     return fail(c, SD_EUNSUPPORTED, "slice window needs %zu B of LDS, device allows %d", lds,
                 lds_max);

@@ -205,7 +205,7 @@ hipError_t launch_slice(hipStream_t s, const SliceArgs* d_args, const int2* d_ma
                         int32_t n_blocks, size_t lds, int wform);
 // one fused slice of a single network, arguments by value
 hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wform);
-size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic = false);
+size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic = false, bool bin = false);
 // add shift to the time fields (t_upd, t_slice0, w_lo, rb_hi) of args[0..n)
 hipError_t launch_shift_args(hipStream_t s, SliceArgs* args, int32_t n, int64_t shift);
 hipError_t launch_count_sm(hipStream_t s, const BuildArgs& a);

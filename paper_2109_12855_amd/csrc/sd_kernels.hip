@@ -851,7 +851,7 @@ struct SliceLds {
   size_t win, carry, dcnt, mask, thr, scr, desc, meta, pm, pb, lagm, tpv, total;
 };
 __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_rows,
-                                                     bool plastic = false) {
+                                                     bool plastic = false, bool bin = false) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
   SliceLds L;
   size_t o = 0;
@@ -862,9 +862,12 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_ro
   L.thr = o;   o = up(o + (size_t)kMaxThr * 4);         // drive thresholds
   L.scr = o;   o = up(o + (size_t)(kSliceThreads / 64 + 2) * 4);
   // one descriptor per spike of a chunk, plus one group of padding so a
-  // wave's last group reads in bounds without clamping its index
+  // wave's last group reads in bounds without clamping its index; binned
+  // records use the same array for their work items (at most P * cap /
+  // kBinSlice <= 1024) and need no meta words, which lets the source-major
+  // layout fit 896-neuron blocks
   L.desc = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 8);  // (start in block, count)
-  L.meta = o;  o = up(o + (size_t)(kSliceThreads + kMaxGroup) * 4);  // lag row, count, population
+  L.meta = o;  o = up(o + (bin ? 0 : (size_t)(kSliceThreads + kMaxGroup) * 4));  // lag row, count, pop.
   // plastic synapses: the block's post-spike masks and earlier spikes, and
   // per spike of a chunk its lag mask and its source's previous spike
   const size_t np = plastic ? 1 : 0;
@@ -876,8 +879,8 @@ __host__ __device__ inline SliceLds slice_lds_layout(int B, int Dmin, int win_ro
   return L;
 }
 
-size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic) {
-  return slice_lds_layout(B, Dmin, win_rows, plastic).total;
+size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic, bool bin) {
+  return slice_lds_layout(B, Dmin, win_rows, plastic, bin).total;
 }
 
 // Plastic synapses: one excitatory weight w (delay d, target row of the
@@ -934,7 +937,7 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
   const int Wd = B >> 5;
   const int Dmin = a.Dmin;
 
-  const SliceLds Lo = slice_lds_layout(B, Dmin, a.win_rows, PL);
+  const SliceLds Lo = slice_lds_layout(B, Dmin, a.win_rows, PL, BIN);
   long long* win = (long long*)(lds_raw + Lo.win);
   float* carry = (float*)(lds_raw + Lo.carry);
   uint8_t* dcnt = lds_raw + Lo.dcnt;
