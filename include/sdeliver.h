@@ -163,7 +163,8 @@ typedef struct {
   int64_t slices;            /* fused slice launches                            */
   int64_t spikes_recorded;   /* entries in the raster                           */
   int32_t overflow;          /* sticky device flags: bit 0 spike-list overflow,  */
-                             /* bit 1 raster overflow, bits 2-3 invalid entries  */
+                             /* bit 1 raster overflow, bits 2-3 invalid entries, */
+                             /* bit 4 a persistent launch's barrier timed out    */
                              /* of an external spike list (SD_EINVAL)            */
 } sd_stats;
 
@@ -235,6 +236,22 @@ sd_status sd_simulate_steps(sd_ctx* ctx, int64_t n_steps);
 /* Validation mode: deliver 1.0 for every synapse so the ring holds exact
  * per-cell event counts (0 = weights, 1 = counts). */
 sd_status sd_set_count_mode(sd_ctx* ctx, int32_t on);
+
+/* Persistent slices (Alg. REF, Sec. 3.2, run for many slices in one
+ * launch): sd_simulate / sd_simulate_steps run up to max_slices whole
+ * slices per cooperative launch, one workgroup per target block.  Each
+ * block keeps its ring window in LDS across the slices (window sums stay in
+ * 64-bit fixed point until their step is updated) and its neurons' state in
+ * registers; slices are separated by grid barriers.  The results are those
+ * of the fused slices up to the FP32 rounding of the ring sums (a sum is
+ * rounded once, not once per delivery).  0 switches back to one launch per
+ * slice.  SD_EUNSUPPORTED unless the net is block-major, closed loop, with
+ * static synapses, blocks of a multiple of 64 and at most 1024 neurons, and
+ * all blocks fit on the device at once; SD_ESTATE before
+ * sd_build_connections.  A grid barrier that waits past its spin limit sets
+ * bit 4 of sd_stats.overflow and ends the launch early (the run's results
+ * are then invalid). */
+sd_status sd_set_persistent(sd_ctx* ctx, int32_t max_slices);
 
 /* Open loop: precompute the virtual sources' spikes for steps
  * [t_now, t_now + n_steps) (outside any timed region). */

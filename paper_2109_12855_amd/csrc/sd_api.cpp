@@ -298,6 +298,8 @@ struct sd_ctx {
   int64_t slices = 0;
   int64_t rec_read = 0;     // raster entries already drained
   SliceLauncher lau;        // this network alone
+  int32_t persist = 0;      // slices per persistent launch (0: one launch per slice)
+  unsigned* pbar = nullptr; // grid-barrier arrivals of a persistent launch
 };
 
 // Independent networks advanced together: every slice of all members is
@@ -406,7 +408,7 @@ struct Layout {
   size_t off_row, off_cursor, off_seg, off_tiles, off_syn, off_dly, off_V, off_y1, off_y2, off_r,
       off_rb, off_list0, off_list1, off_cnt, off_rec, off_wte, off_wti, off_thr, off_p64, off_p32,
       off_counters, off_overflow, off_bins, off_bcnt, off_spill, off_sflag, off_ext, off_extcnt,
-      off_pmask, off_pbefore, off_aux0, off_aux1, off_prev0, off_prev1, total;
+      off_pmask, off_pbefore, off_aux0, off_aux1, off_prev0, off_prev1, off_pbar, total;
 };
 
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS of one gfx950 workgroup
@@ -569,6 +571,7 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   L->off_p32 = take(8 * 4);
   L->off_counters = take(8 * 8);
   L->off_overflow = take(4);
+  L->off_pbar = take(4);
   const size_t brec = c->wform == SD_W_FP32 ? 8 : 4;
   L->off_bins = take(L->sm ? (size_t)L->NB * L->bin_P * L->bin_cap * brec : 0);
   L->off_bcnt = take(L->sm ? (size_t)L->NB * L->bin_P * 4 : 0);
@@ -901,6 +904,7 @@ sd_status sd_create(const sd_config* cfg, void* hip_stream, void* d_arena, size_
   c->prop32 = (float*)(A + L.off_p32);
   c->counters = (unsigned long long*)(A + L.off_counters);
   c->overflow = (int32_t*)(A + L.off_overflow);
+  c->pbar = (unsigned*)(A + L.off_pbar);
 
   // tables (host, FP64 -> FP32 / BF16 codes)
   const sd_config& g = *cfg;
@@ -1264,9 +1268,59 @@ sd_status next_fused_slice(sd_ctx* c, int32_t m, SliceArgs* out) {
   *out = a;
   return SD_OK;
 }
+// S whole slices from an aligned t_now in one persistent launch; the host
+// state advances exactly as S fused slices would advance it.
+sd_status run_persistent(sd_ctx* c, int32_t S) {
+  const sd_config& g = c->cfg;
+  const int32_t Dmin = g.d_min;
+  SliceArgs a = base_args(c);
+  a.in_cap = c->list_cap;
+  a.zero_cnt = nullptr;
+  const int32_t pend0 = c->pend_open ? 1 : 0;
+  HIP_TRY(c, hipMemsetAsync(c->pbar, 0, 4, c->stream));
+  HIP_TRY(c, launch_persist(c->stream, a, c->list, c->cnt3, c->cur, c->ci, pend0, S, c->t_now,
+                            c->rb_hi, c->pbar, c->lau.lds, g.wform));
+  for (int32_t k = 0; k < S; ++k) {
+    if (k > 0 || pend0) c->rb_hi = std::max(c->rb_hi, c->t_now + g.d_max);
+    c->cur ^= 1;
+    c->ci = (c->ci + 1) % 3;
+    c->pend_open = true;
+    c->pend_t0 = c->t_now;
+    c->t_now += Dmin;
+    c->slices += 1;
+  }
+  return SD_OK;
+}
 }  // namespace
 
 extern "C" {
+
+sd_status sd_set_persistent(sd_ctx* c, int32_t max_slices) {
+  if (!c) return SD_EINVAL;
+  if (max_slices < 0) return fail(c, SD_EINVAL, "max_slices must be >= 0");
+  if (max_slices == 0) {
+    c->persist = 0;
+    return SD_OK;
+  }
+  if (!c->built) return fail(c, SD_ESTATE, "build_connections first");
+  const sd_config& g = c->cfg;
+  if (c->sm || g.plastic || open_loop(g))
+    return fail(c, SD_EUNSUPPORTED,
+                "persistent slices need a block-major, closed-loop net with static synapses");
+  if (c->B > kSliceThreads || c->B % 64 != 0)
+    return fail(c, SD_EUNSUPPORTED, "persistent slices need blocks of a multiple of 64 and at "
+                "most %d neurons", kSliceThreads);
+  int coop = 0, n_cu = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int64_t grid = 8 * (int64_t)((c->NB + 7) / 8);
+  const int occ = persist_occupancy(g.wform, c->lau.lds);
+  if (!coop || (int64_t)occ * n_cu < grid)
+    return fail(c, SD_EUNSUPPORTED, "persistent slices need all %lld blocks resident at once "
+                "(%d per CU on %d CUs)", (long long)grid, occ, n_cu);
+  c->persist = max_slices;
+  return SD_OK;
+}
 
 sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
   if (!c || n_steps < 0) return fail(c, SD_EINVAL, "bad step count");
@@ -1290,6 +1344,14 @@ sd_status sd_simulate_steps(sd_ctx* c, int64_t n_steps) {
       if (s == SD_OK) s = sd_update_neurons(c, m);
       if (s != SD_OK) return s;
       left -= m;
+      continue;
+    }
+    if (c->persist > 0 && left >= Dmin && (!c->pend_open || c->pend_t0 + Dmin == c->t_now)) {
+      const int32_t S = (int32_t)std::min<int64_t>(left / Dmin, c->persist);
+      sd_status s = flush();
+      if (s == SD_OK) s = run_persistent(c, S);
+      if (s != SD_OK) return s;
+      left -= (int64_t)S * Dmin;
       continue;
     }
     const int32_t m = (int32_t)std::min<int64_t>(left, Dmin);

@@ -1739,6 +1739,347 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
 }
 
 // ---------------------------------------------------------------------------
+// persistent multi-slice kernel (block-major, static synapses, closed loop)
+// ---------------------------------------------------------------------------
+// One cooperative launch runs S consecutive fused slices of a network whose
+// blocks are all resident at once (one workgroup per block).  A workgroup
+// keeps its block's delivery window in LDS for the whole launch, as a ring
+// of Dmax rows indexed by step modulo Dmax: a delivery adds into the rows of
+// steps [w_lo, w_lo + Dmax) (Alg. REF, Sec. 3.2), the update reads the rows
+// of its steps and clears them for reuse, and only at the end do the rows
+// due after the last slice go to the HBM ring.  Window sums therefore stay
+// in fixed point until their step is updated.  Neuron state stays in
+// registers.  Slices are separated by a grid barrier, since the spike list
+// one slice writes is read by every block in the next; the lists and their
+// three rotating counters are those of the one-launch-per-slice path.
+constexpr long kBarSpin = 1L << 22;  // polls before a grid barrier gives up
+
+// All workgroups of the launch wait here; the release fence publishes this
+// workgroup's global writes (spike list, counters) and the acquire fence
+// drops stale lines of other workgroups' writes.  A wait past kBarSpin polls
+// sets bit 4 of the overflow flags, and every workgroup then leaves.
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* overflow) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255) == 0 &&
+          (__hip_atomic_load(overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 16)) {
+        ok = 0;
+        break;
+      }
+      if (spins > kBarSpin) {
+        atomicOr(overflow, 16);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+struct PersistArgs {
+  SliceArgs a;         // network constants; time and list fields of slice 0
+  uint32_t* lists[2];  // the two spike-list buffers
+  int32_t* cnt3;       // the three rotating list counters
+  int32_t cur0, ci0;   // slice 0 reads lists[cur0] with count cnt3[ci0]
+  int32_t pend0;       // slice 0 delivers that list (else no delivery)
+  int32_t S;           // slices
+  int32_t per_xcd;     // blocks per XCD (grid = 8 * per_xcd)
+  int64_t t0;          // first step of slice 0
+  int64_t rb_hi0;      // HBM ring rows of steps below this hold earlier sums
+  unsigned* bar;       // grid-barrier arrivals (zero at launch)
+};
+
+template <int WF>
+__global__ void __launch_bounds__(kSliceThreads) k_persist(PersistArgs p) {
+  const PersistArgs* pp = (const PersistArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  const SliceArgs& a = pp->a;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int gx = blockIdx.x;
+  const int b = (gx & 7) * pp->per_xcd + (gx >> 3);
+  const bool live = b < a.NB;  // padding workgroups only take part in the barriers
+  const int B = a.B, Dmin = a.Dmin, R = a.Dmax, NB = a.NB;
+  const int RB = R * B;
+  const int64_t j0 = (int64_t)(live ? b : 0) * B;
+  const int nb = live ? (int)((a.N - j0) < B ? (a.N - j0) : B) : 0;
+  const int Wd = B >> 5;
+  const SliceLds Lo = slice_lds_layout(B, Dmin, R);
+  long long* win = (long long*)(lds_raw + Lo.win);
+  uint8_t* dcnt = lds_raw + Lo.dcnt;
+  uint32_t* mask = (uint32_t*)(lds_raw + Lo.mask);
+  uint32_t* thr = (uint32_t*)(lds_raw + Lo.thr);
+  int32_t* scr = (int32_t*)(lds_raw + Lo.scr);
+  uint2* desc = (uint2*)(lds_raw + Lo.desc);
+  uint32_t* meta = (uint32_t*)(lds_raw + Lo.meta);
+  __shared__ int s_next, s_base;
+  __shared__ unsigned long long s_rbase, s_ev;
+
+  for (int i = tid; i < RB; i += kSliceThreads) win[i] = 0;
+  if (tid < kMaxThr) thr[tid] = (tid < a.n_thr) ? a.thr[tid] : 0xffffffffu;
+  if (tid == 0) s_ev = 0;
+  // neuron state of this thread's neuron, in registers for the launch
+  const bool own = tid < nb;
+  const int64_t gn = j0 + (own ? tid : 0);
+  float V = 0.f, y1 = 0.f, y2 = 0.f;
+  int rf = 0;
+  if (own) {
+    V = a.V[gn];
+    rf = a.r[gn];
+    if (a.model == MODEL_ALPHA) {
+      y1 = a.y1[gn];
+      y2 = a.y2[gn];
+    }
+  }
+  const float P11 = a.prop[0], P21 = a.prop[1], P22 = a.prop[2], P31 = a.prop[3];
+  const float P32 = a.prop[4], P33 = a.prop[5], P30Ie = a.prop[6], insc = a.prop[7];
+  const float inv = a.fx_inv, drive_w = a.drive_w;
+  const float e_l = a.e_l, v_th = a.v_th, v_reset = a.v_reset;
+  const int ref_steps = a.ref_steps;
+  const bool delta = a.model == MODEL_DELTA;
+  float m0e = a.wm0_e, m0i = a.wm0_i, m1e = a.wm1_e, m1i = a.wm1_i;
+  asm volatile("" : "+s"(m0e), "+s"(m0i), "+s"(m1e), "+s"(m1i));
+  unsigned long long spk_all = 0, in_all = 0;
+  const int64_t t0 = pp->t0, rb_hi0 = pp->rb_hi0;
+  const int S = pp->S;
+  int cur = pp->cur0, ci = pp->ci0;
+  bool ok = true;
+  __syncthreads();  // window, thresholds
+
+  for (int k = 0; k < S && ok; ++k) {
+    const int64_t w_lo = t0 + (int64_t)k * Dmin;  // first step of slice k
+    const bool deliver = k > 0 || pp->pend0;
+    const uint32_t* in_list = pp->lists[cur];
+    int32_t* in_cnt = pp->cnt3 + ci;
+    uint32_t* out_list = pp->lists[cur ^ 1];
+    int32_t* out_cnt = pp->cnt3 + (ci + 1) % 3;
+    // the counter of slice k + 1's list starts at zero; its last reader was
+    // slice k - 1's delivery, before the barrier
+    if (gx == 0 && tid == 0) __hip_atomic_store(pp->cnt3 + (ci + 2) % 3, 0, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = tid; i < Dmin * Wd; i += kSliceThreads) mask[i] = 0u;
+    // ---- drive counts of the slice's steps (Philox, as in the fused slice)
+    {
+      const int64_t c0 = w_lo >> 3, c1 = (w_lo + Dmin - 1) >> 3;
+      const int n_tasks = live ? (int)(c1 - c0 + 1) * nb : 0;
+      for (int task = tid; task < n_tasks; task += kSliceThreads) {
+        const int n = task % nb;
+        const int64_t c = c0 + task / nb;
+        uint64_t rr[4];
+        philox(a.seed, STREAM_DRIVE, (uint64_t)(j0 + n), (uint64_t)c, rr);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t t = c * 8 + q;
+          if (t < w_lo || t >= w_lo + Dmin) continue;
+          const uint64_t word = rr[q >> 1];
+          const uint32_t u = (q & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+          int cnt = 0;
+          while (cnt < a.n_thr && u >= thr[cnt]) ++cnt;
+          dcnt[(int)(t - w_lo) * B + n] = (uint8_t)cnt;
+        }
+      }
+    }
+    // ---- delivery of the previous slice's spikes into the window ring ----
+    if (deliver && live) {
+      constexpr int G = SynGroup<WF>::n;
+      const int base = (int)(w_lo % R);  // ring row of step w_lo
+      int64_t total = __hip_atomic_load(in_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
+      uint64_t ev = 0;
+      for (int64_t c0 = 0; c0 < total; c0 += kSliceThreads) {
+        const int n_c = (int)((total - c0) < kSliceThreads ? (total - c0) : kSliceThreads);
+        __syncthreads();  // the previous chunk's descriptors are no longer read
+        if (tid < n_c) {
+          const uint32_t ent = in_list[c0 + tid];
+          const uint32_t src = ent >> 5;
+          const int lag = (int)(ent & 31u);
+          uint2 sg = make_uint2(0u, 0u);
+          if (lag < Dmin && (int64_t)src < a.n_src) sg = a.seg[(int64_t)src * NB + b];
+          else atomicOr(a.overflow, 4);
+          desc[tid] = sg;
+          // ring offset of the spike's arrival rows: row (base + lag + delay
+          // - Dmin) mod R, the modulo taken per synapse
+          meta[tid] = ((uint32_t)((lag + base) * B) << 7) | (sg.y < 65u ? sg.y : 65u) |
+                      (((int64_t)src >= a.src_e_end) ? 0x80000000u : 0u);
+          ev += sg.y;
+        }
+        if (tid == 0) s_next = 0;
+        __syncthreads();
+        for (;;) {
+          int g0 = 0;
+          if (lane == 0)
+            g0 = __hip_atomic_fetch_add(&s_next, G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          g0 = __builtin_amdgcn_readfirstlane(g0);
+          if (g0 >= n_c) break;
+          const int n_here = (n_c - g0) < G ? (n_c - g0) : G;
+          SynRaw<WF> raw[G];
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            const uint2 d = desc[g0 + u];  // past the chunk: stale or padding, masked
+            const bool on = (u < n_here) & (lane < (int)d.y);
+            raw[u] = syn_fetch<WF>(a.syn, a.syn_dly, on ? d.x + (uint32_t)lane : 0u);
+          }
+          bool any_long = false;
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            const uint32_t m = __builtin_amdgcn_readfirstlane(meta[g0 + u]);
+            any_long |= (u < n_here) & ((m & 127u) > 64u);
+            const bool inh = (int32_t)m < 0;
+            if ((u < n_here) & (lane < (int)(m & 127u)) & (lane < 64)) {
+              int slot, v;
+              syn_decode<WF>(raw[u], (int32_t)j0, Dmin, B, inh ? m0i : m0e, inh ? m1i : m1e,
+                             slot, v);
+              uint32_t x = ((m >> 7) & 0xffffffu) + (uint32_t)slot;
+              x = min(x, x - (uint32_t)RB);  // below 2 R B: one wrap at most
+              __hip_atomic_fetch_add((unsigned long long*)&win[x], (unsigned long long)(long long)v,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+          // segments longer than one wave
+          if (any_long) {
+            for (int u = 0; u < n_here; ++u) {
+              const uint2 d = desc[g0 + u];
+              const uint32_t m = meta[g0 + u];
+              const int sl = __builtin_amdgcn_readfirstlane((int)d.y);
+              const bool inh = (int32_t)m < 0;
+              for (int e0 = 64; e0 < sl; e0 += 64) {
+                const bool on = lane + e0 < sl;
+                const SynRaw<WF> xr =
+                    syn_fetch<WF>(a.syn, a.syn_dly, on ? d.x + (uint32_t)(e0 + lane) : 0u);
+                if (on) {
+                  int slot, v;
+                  syn_decode<WF>(xr, (int32_t)j0, Dmin, B, inh ? m0i : m0e, inh ? m1i : m1e,
+                                 slot, v);
+                  uint32_t x = ((m >> 7) & 0xffffffu) + (uint32_t)slot;
+                  x = min(x, x - (uint32_t)RB);
+                  __hip_atomic_fetch_add((unsigned long long*)&win[x],
+                                         (unsigned long long)(long long)v, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
+      if (lane == 0 && ev)
+        __hip_atomic_fetch_add(&s_ev, (unsigned long long)ev, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (b == 0 && tid == 0) in_all += (unsigned long long)total;
+    }
+    __syncthreads();  // window adds and drive counts complete
+    // ---- update of the slice's Dmin steps, reading (and clearing) the ring
+    if (own) {
+      for (int s = 0; s < Dmin; ++s) {
+        const int64_t t = w_lo + s;
+        long long* cell = &win[(int)(t % R) * B + tid];
+        float in = from_fixed(*cell, inv);
+        *cell = 0;
+        if (t < rb_hi0) in += a.rb[(t % a.L) * a.N + gn];  // sums from before the launch
+        const float drive = (float)dcnt[s * B + tid] * drive_w;
+        if (delta) {
+          if (rf > 0) --rf;
+          else V = e_l + P33 * (V - e_l) + P30Ie + in + drive;
+        } else {
+          if (rf == 0) V = e_l + P31 * y1 + P32 * y2 + P33 * (V - e_l) + P30Ie;
+          else --rf;
+          const float y2n = P21 * y1 + P22 * y2;
+          y1 = P11 * y1 + insc * (in + drive);
+          y2 = y2n;
+        }
+        const bool spk = V >= v_th;
+        if (spk) {
+          V = v_reset;
+          rf = ref_steps;
+        }
+        const uint64_t bal = __ballot(spk);
+        if (lane == 0) {
+          const int w0 = (tid - lane) >> 5;
+          mask[s * Wd + w0] = (uint32_t)bal;
+          mask[s * Wd + w0 + 1] = (uint32_t)(bal >> 32);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- compaction into slice k + 1's list, (lag, neuron) ordered -------
+    if (live) {
+      const int nq = Dmin * Wd;
+      for (int q0 = 0; q0 < nq; q0 += kSliceThreads) {
+        const int q = q0 + tid;
+        uint32_t m = (q < nq) ? mask[q] : 0u;
+        int tot;
+        const int ex = block_excl_scan<int>(__popc(m), scr, tot);
+        if (tot == 0) continue;
+        if (tid == 0) {
+          s_base = atomicAdd(out_cnt, tot);
+          s_rbase = a.rec ? atomicAdd(a.rec_n, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        const int64_t lbase = s_base;
+        const unsigned long long rbase = s_rbase;
+        __syncthreads();
+        int pos = ex;
+        const int lg = q / Wd;
+        const int nbase = (q % Wd) * 32;
+        while (m) {
+          const int bit = __ffs(m) - 1;
+          m &= m - 1;
+          const int64_t g = j0 + nbase + bit;
+          if (lbase + pos < a.out_cap) out_list[lbase + pos] = ((uint32_t)g << 5) | (uint32_t)lg;
+          else atomicOr(a.overflow, 1);
+          if (a.rec) {
+            const unsigned long long rp = rbase + (unsigned long long)pos;
+            if ((int64_t)rp < a.rec_cap) a.rec[rp] = make_uint2((uint32_t)(w_lo + lg), (uint32_t)g);
+            else atomicOr(a.overflow, 2);
+          }
+          ++pos;
+        }
+        if (tid == 0) spk_all += (unsigned long long)tot;
+      }
+    }
+    cur ^= 1;
+    ci = (ci + 1) % 3;
+    if (k + 1 < S) ok = grid_barrier(pp->bar, (unsigned)gridDim.x * (unsigned)(k + 1), a.overflow);
+  }
+  if (!live) return;
+  // ---- rows due after the last slice go to the HBM ring ---------------------
+  const int64_t t_end = t0 + (int64_t)S * Dmin;
+  const bool delivered = S > 1 || pp->pend0;
+  if (ok && delivered && own) {
+    const int64_t hi = t_end - Dmin + R;  // end of the last delivery window
+    for (int64_t t = t_end; t < hi; ++t) {
+      const float v = from_fixed(win[(int)(t % R) * B + tid], inv);
+      float* cell = a.rb + (t % a.L) * a.N + gn;
+      *cell = (t < rb_hi0) ? *cell + v : v;
+    }
+  }
+  if (own) {
+    a.V[gn] = V;
+    a.r[gn] = rf;
+    if (a.model == MODEL_ALPHA) {
+      a.y1[gn] = y1;
+      a.y2[gn] = y2;
+    }
+  }
+  __syncthreads();  // s_ev complete
+  if (tid == 0) {
+    if (s_ev) atomicAdd(a.ev_count, s_ev);
+    if (in_all) atomicAdd(a.spk_in_count, in_all);
+    if (spk_all) atomicAdd(a.spk_count, spk_all);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // helpers: ring gap zeroing, open-loop input schedule, decoded export
 // ---------------------------------------------------------------------------
 __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64_t t_hi) {
@@ -1969,6 +2310,47 @@ hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wfor
   if (kSliceThreads - a.B < a.B) launch_slice1_as<true>(s, sa, lds, wform);
   else launch_slice1_as<false>(s, sa, lds, wform);
   return hipGetLastError();
+}
+
+// Workgroups per CU that a persistent launch of this weight form can hold.
+int persist_occupancy(int wform, size_t lds) {
+  int occ = 0;
+  hipError_t e;
+  switch (wform) {
+    case WF_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persist<WF_FP32>, kSliceThreads, lds); break;
+    case WF_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persist<WF_BF16>, kSliceThreads, lds); break;
+    case WF_PACKED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persist<WF_PACKED>, kSliceThreads, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persist<WF_BF16_RESID>, kSliceThreads, lds); break;
+  }
+  return e == hipSuccess ? occ : 0;
+}
+
+// Cooperative launch: the runtime refuses a grid that cannot be resident at
+// once, so the grid barriers cannot wait on a workgroup that never starts.
+hipError_t launch_persist(hipStream_t s, const SliceArgs& a, uint32_t* const lists[2],
+                          int32_t* cnt3, int32_t cur0, int32_t ci0, int32_t pend0, int32_t S,
+                          int64_t t0, int64_t rb_hi0, unsigned* bar, size_t lds, int wform) {
+  PersistArgs p;
+  p.a = a;
+  p.lists[0] = lists[0];
+  p.lists[1] = lists[1];
+  p.cnt3 = cnt3;
+  p.cur0 = cur0;
+  p.ci0 = ci0;
+  p.pend0 = pend0;
+  p.S = S;
+  p.per_xcd = (a.NB + 7) / 8;
+  p.t0 = t0;
+  p.rb_hi0 = rb_hi0;
+  p.bar = bar;
+  void* args[] = {&p};
+  const dim3 grid((unsigned)(8 * p.per_xcd)), block(kSliceThreads);
+  switch (wform) {
+    case WF_FP32: return hipLaunchCooperativeKernel((const void*)k_persist<WF_FP32>, grid, block, args, lds, s);
+    case WF_BF16: return hipLaunchCooperativeKernel((const void*)k_persist<WF_BF16>, grid, block, args, lds, s);
+    case WF_PACKED: return hipLaunchCooperativeKernel((const void*)k_persist<WF_PACKED>, grid, block, args, lds, s);
+    default: return hipLaunchCooperativeKernel((const void*)k_persist<WF_BF16_RESID>, grid, block, args, lds, s);
+  }
 }
 
 // Captured batches: the argument sets of a period of slices move on by
