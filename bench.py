@@ -88,6 +88,32 @@ def copy_probe():
     _log(f"copy probe: 3 x {COPY_PROBE_BYTES} B read + written")
 
 
+def copy_bandwidth(nbytes: int = 1 << 31, reps: int = 10) -> dict:
+    """Achieved HBM bandwidth of a plain device copy (read + write of nbytes
+    each), timed with HIP events: the practical ceiling the slice's
+    algorithmic GB/s is also compared with."""
+    import torch
+
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": nbytes, "us": round(ms * 1e3, 1),
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def _log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -553,6 +579,8 @@ def main():
                     help="skip the one-step-slice (d_min = 0.1 ms) workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the autotuned 64-network batched sweep")
+    ap.add_argument("--no-share-repetitions", action="store_true",
+                    help="skip the headline's repetitions with seeds 1, 2, 3")
     ap.add_argument("--no-share-tuning", action="store_true",
                     help="skip the binning-parameter autotuning of the brain-scale share")
     ap.add_argument("--copy-probe", action="store_true",
@@ -575,7 +603,7 @@ def main():
     if args.headline_only:
         args.no_cpu = args.no_cpu_paper = args.no_share_fp32 = args.no_precision = True
         args.no_rate_cv = args.no_short_delay = args.no_sweep = args.no_plastic = True
-        args.no_share_tuning = True
+        args.no_share_tuning = args.no_share_repetitions = True
         args.forms = ""
     if args.forms_only:
         forms_all = alpha_forms()
@@ -592,6 +620,16 @@ def main():
     if args.copy_probe:
         copy_probe()
     share = {"bf16_resid": head}
+    if not args.no_share_repetitions:
+        reps = [time_net(dict(share_cfg(2), seed=sd, name=f"alpha_share_1125000_bf16_resid_seed{sd}"),
+                         args.steps, args.warmup, open_loop=True) for sd in (1, 2, 3)]
+        ev = np.array([r["events_per_s"] for r in reps])
+        share["repetitions"] = {"seeds": [1, 2, 3],
+                                "us_per_slice": [r["us_per_slice"] for r in reps],
+                                "events_per_s": ev.tolist(), "mean_events_per_s": float(ev.mean()),
+                                "sd_events_per_s": float(ev.std(ddof=1)),
+                                "mean_roofline_frac": float(np.mean([r["roofline_frac"] for r in reps]))}
+        _log("brain share repetitions: " + json.dumps(share["repetitions"]))
     if not args.no_share_fp32:
         share["fp32"] = time_net(share_cfg(0), args.steps, args.warmup, open_loop=True)
         _log("brain share fp32: " + json.dumps(share["fp32"]))
@@ -641,13 +679,20 @@ def main():
         cpu_paper = cpu_paper_algorithms()
         _log("cpu paper algorithms: " + json.dumps(cpu_paper))
     prof = profile_json(SHARE_TRAFFIC)
+    # (not in the profiled headline-only runs: the counter calibration copy
+    # must be the only copy there)
+    copy = None if args.headline_only else copy_bandwidth()
+    if copy:
+        _log("copy reference: " + json.dumps(copy))
     roof = {"bound": "hbm", "achieved": round(head["alg_gbs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(head["alg_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": (round(prof["fetch_bytes_per_slice"] + prof["write_bytes_per_slice"])
                         if prof else None),
             "kernel": "one slice: binning pass + fused accumulate/update kernel",
             "alg_bytes_per_slice": head["alg_bytes_per_slice"],
-            "l2_hit_rate": prof.get("l2_hit_rate") if prof else None}
+            "l2_hit_rate": prof.get("l2_hit_rate") if prof else None,
+            "copy_reference_gbs": round(copy["gbs"], 1) if copy else None,
+            "frac_of_copy": round(head["alg_gbs"] / copy["gbs"], 4) if copy else None}
     line = {
         "metric": "synaptic events delivered/s",
         "value": head["events_per_s"],
