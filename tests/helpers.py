@@ -2,8 +2,9 @@
 
 A raster mismatch between the FP32 GPU path and the FP64 oracle is
 *explained* only when the oracle's membrane potential at that step lay within
-``eps`` of threshold (a rounding-level tie); after the first explained
-mismatch the comparison stops, since the network is chaotic.
+a tolerance of threshold (a rounding-level tie), the tolerance derived from
+the measured FP32 drift; after the first explained mismatch the comparison
+stops, since the network is chaotic.
 """
 from __future__ import annotations
 
@@ -17,25 +18,6 @@ def _by_step(st, idx):
     for t, j in zip(st.tolist(), idx.tolist()):
         d.setdefault(t, set()).add(j)
     return d
-
-
-def compare_rasters(cfg: dict, gpu_st, gpu_idx, horizon: int, eps: float):
-    """Return (first_mismatch_step or None, explained, details)."""
-    ost, oidx = oracle.Net(cfg).simulate(horizon)
-    g = _by_step(np.asarray(gpu_st)[np.asarray(gpu_st) < horizon],
-                 np.asarray(gpu_idx)[np.asarray(gpu_st) < horizon])
-    o = _by_step(ost, oidx)
-    steps = sorted(set(g) | set(o))
-    for t in steps:
-        a, b = g.get(t, set()), o.get(t, set())
-        if a != b:
-            diff = sorted(a ^ b)
-            ref = oracle.Net(cfg)
-            ref.simulate(t + 1)
-            vpre = ref.vpre()
-            margins = [abs(vpre[j] - cfg["v_th"]) for j in diff]
-            return t, all(m <= eps for m in margins), dict(diff=diff, margins=margins)
-    return None, True, {}
 
 
 def rate_cv(st, idx, n: int, t_lo: int, t_hi: int, h: float):
@@ -62,7 +44,7 @@ def _ulp32(x: float) -> float:
 
 
 def spike_exact(cfg: dict, gpu, ref_factory, horizon: int, min_exact: int, safety: float = 2.0,
-                tgt=None):
+                tgt=None, raster: list | None = None):
     """Tie-aware raster comparison with a tolerance derived from measurement.
 
     ``gpu`` is a built context (record_spikes on, at step 0) and
@@ -79,8 +61,10 @@ def spike_exact(cfg: dict, gpu, ref_factory, horizon: int, min_exact: int, safet
     before the threshold test lay within the tolerance of V_th for every
     neuron involved, and the comparison stops at the first one (chaos).
     ``tgt`` = (lo, hi): the oracle holds only those targets (open loop) and
-    only they are compared.  Returns (eps, first mismatch step or None,
-    spikes compared, the oracle advanced to ``horizon``)."""
+    only they are compared.  ``raster``: a list that receives the GPU's
+    compared (steps, ids), which this call drains from the context.  Returns
+    (eps, first mismatch step or None, spikes compared, the oracle advanced
+    to ``horizon``)."""
     lo, hi = tgt if tgt is not None else (0, int(cfg["n_exc"] + cfg["n_inh"]))
 
     def spikes():
@@ -102,6 +86,8 @@ def spike_exact(cfg: dict, gpu, ref_factory, horizon: int, min_exact: int, safet
     gpu.simulate_steps(horizon - min_exact)
     ost2, oid2 = ref.simulate(horizon - min_exact)
     g2_st, g2_id = spikes()
+    if raster is not None:
+        raster.append((np.concatenate([g_st, g2_st]), np.concatenate([g_id, g2_id])))
     g = _by_step(np.concatenate([g_st, g2_st]), np.concatenate([g_id, g2_id]))
     o = _by_step(np.concatenate([ost1, ost2]), np.concatenate([oid1, oid2]))
     n_cmp = 0

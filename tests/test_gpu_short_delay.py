@@ -10,10 +10,11 @@ delivery's exact window sums once.
 import numpy as np
 import pytest
 
+import oracle
 from paper_2109_12855_amd import sdeliver
 from paper_2109_12855_amd import workloads as W
 
-from helpers import compare_rasters
+from helpers import spike_exact
 from test_gpu_parity import _replay_check
 
 pytestmark = pytest.mark.gpu
@@ -39,11 +40,9 @@ def test_closed_loop_one_step_slices(layout):
     cfg = dict(W.tiny(model=1, n=400, k=80, seed=12, d_lo=1, d_hi=20), record_spikes=1,
                layout=layout)
     net = sdeliver.Net(cfg).build()
-    net.simulate_steps(500)
-    st, idx = net.spikes()
-    assert len(st) > 10
-    t_bad, explained, info = compare_rasters(cfg, st, idx, 500, eps=1e-3)
-    assert t_bad is None or explained, (t_bad, info)
+    ras = []
+    spike_exact(cfg, net, lambda: oracle.Net(cfg), horizon=500, min_exact=50, raster=ras)
+    assert len(ras[0][0]) > 10
 
 
 def test_full_size_layouts_agree():

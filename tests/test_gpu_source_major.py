@@ -15,7 +15,7 @@ import oracle
 from paper_2109_12855_amd import sdeliver
 from paper_2109_12855_amd import workloads as W
 
-from helpers import compare_rasters
+from helpers import spike_exact
 from test_gpu_parity import _dev, _replay_check, _tiny_cases
 
 pytestmark = pytest.mark.gpu
@@ -57,11 +57,9 @@ def test_replay_delivery(case):
 def test_closed_loop_tiny(case):
     cfg = dict(_tiny_cases()[case], record_spikes=1, layout=SM)
     net = sdeliver.Net(cfg).build()
-    net.simulate_steps(400)
-    st, idx = net.spikes()
-    assert len(st) > 10
-    t_bad, explained, info = compare_rasters(cfg, st, idx, 400, eps=1e-3)
-    assert t_bad is None or explained, (t_bad, info)
+    ras = []
+    spike_exact(cfg, net, lambda: oracle.Net(cfg), horizon=400, min_exact=40, raster=ras)
+    assert len(ras[0][0]) > 10
 
 
 def _run(cfg, steps):
@@ -162,11 +160,9 @@ def test_open_loop_against_oracle(layout):
     net = sdeliver.Net(cfg).build()
     assert net.sizes["layout"] == layout
     net.prepare_input(300)
-    net.simulate_steps(300)
-    st, idx = net.spikes()
-    assert len(st) > 5
-    t_bad, explained, info = compare_rasters(cfg, st, idx, 300, eps=1e-3)
-    assert t_bad is None or explained, (t_bad, info)
+    ras = []
+    spike_exact(cfg, net, lambda: oracle.Net(cfg), horizon=300, min_exact=30, raster=ras)
+    assert len(ras[0][0]) > 5
 
 
 @pytest.mark.parametrize("layout", [sdeliver.SD_LAYOUT_BLOCK, SM])
