@@ -429,7 +429,6 @@ int32_t auto_bin_cap(const sd_config& c, const Layout& L) {
 // Block-major geometry and its limits (LDS window, u16/packed offsets,
 // buffer-resource range, 32-bit segment pointers).
 sd_status block_major_fits(const sd_config* c, Layout* L, std::string* why) {
-  const int64_t K = (int64_t)c->k_exc + c->k_inh;
   L->B = auto_block(*c, L->N);
   L->NB = (int32_t)((L->N + L->B - 1) / L->B);
   if (L->B > 65536 && c->wform != SD_W_FP32) {

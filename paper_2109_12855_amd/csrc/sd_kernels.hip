@@ -1525,7 +1525,6 @@ __device__ __forceinline__ void slice_block(const SliceArgs& a, const int b) {
           in_s[q] = on ? in : 0.f;
           dr_s[q] = on ? (float)dc[q] * drive_w : 0.f;
         }
-#pragma unroll
         for (int q = 0; q < kSteps; ++q) {
         const int s = s0 + q;
         if (s >= n_upd) break;
