@@ -470,14 +470,17 @@ sd_status make_layout(const sd_config* c, Layout* L, std::string* why) {
   }
   if (L->sm) {
     // record word: offset in a part of 2^tbits targets, then the delay
-    // offset in dbits (tbits + dbits = 24); H parts cover the targets
+    // offset in dbits (tbits + dbits <= 24); H parts cover the targets.
+    // Parts of at most 2^18 targets: the binning pass takes a part's
+    // segments together, so that a sorting chunk's events fall into that
+    // part's few hundred blocks and each block's run is long
     int dbits = 1;
     while ((1 << dbits) < c->d_max - c->d_min + 1) ++dbits;
-    L->tbits = kRecWordBits - dbits;
+    L->tbits = std::min(kRecWordBits - dbits, kPartBits);
     L->H = (int32_t)((L->N + (1LL << L->tbits) - 1) >> L->tbits);
     if (dbits > 8 || L->H > kMaxParts || L->n_src >= (1LL << 27)) {
       *why = "source-major layout holds at most 2^27 sources, d_max - d_min < 256 and "
-             "4 target parts of 2^(24 - delay bits) targets";
+             "64 target parts of 2^18 targets";
       return SD_EUNSUPPORTED;
     }
     // The events are binned by target block and accumulated in the same LDS

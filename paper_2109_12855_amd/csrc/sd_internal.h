@@ -173,18 +173,20 @@ struct BinArgs {
 // FP32 form adds the f32 weight as a second word.
 constexpr int kBinSlotBits = 15;
 constexpr int kBinThreads = 1024;
-constexpr int kBinSpikes = 512;   // spikes resolved per descriptor batch
+constexpr int kBinSpikes = 1024;  // segment entries resolved per descriptor batch
 constexpr int kBinMaxU = 12;      // events per thread per sorting chunk (4-byte records; 16 spills)
 constexpr int kBinMaxU8 = 8;      // the same for 8-byte records (12 spill)
 constexpr int kBinProducers = 256;
 constexpr int kBinMaxCap = 1024;  // records per region (consumer work items <= 1024)
 constexpr int kBinSlice = 256;    // records per consumer work item
+constexpr int kBinSegTab = 8192;  // binning: event -> segment-entry lookup entries per batch
 constexpr int kBinGrp = 4;        // binning: LDS reads issued before one wait (divides kBinMaxU)
 size_t bin_lds_bytes(int NB, int U, bool w8);
 // source-major record word: offset in part (tbits) | delay - d_min (dbits),
-// tbits + dbits = 24, the top byte holds the BF16 weight's high byte
+// tbits + dbits <= 24, the top byte holds the BF16 weight's high byte
 constexpr int kRecWordBits = 24;
-constexpr int kMaxParts = 4;
+constexpr int kMaxParts = 64;
+constexpr int kPartBits = 18;  // source-major target parts of at most 2^18 targets
 
 // launch wrappers (sd_kernels.hip)
 hipError_t launch_propagators(hipStream_t s, int model, double h, double tau_m, double tau_syn,

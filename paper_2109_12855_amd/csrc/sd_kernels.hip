@@ -415,14 +415,17 @@ __global__ void __launch_bounds__(256) k_fill_sm(BuildArgs a) {
 // (Sec. 3.2: segments shrink as the network is spread over more processes).
 // The slice's events are instead sorted by target block on the fly: each of
 // P workgroups takes a contiguous share of the spike list, walks the spikes'
-// segments (coalesced), and sorts chunks of U * 1024 events by block in LDS
-// (a returning LDS atomic on the block's counter gives an event's rank, a
-// block scan the bin starts).  Each bin's run is then appended to the
+// (spike, target part) segments part by part (coalesced), and sorts chunks
+// of U * 1024 events by block in LDS (a returning LDS atomic on the block's
+// counter gives an event's rank, a block scan over the chunk's part's blocks
+// the bin starts).  Taking a part's segments together keeps a chunk's events
+// in a few hundred blocks, so each block's run of a chunk is tens of records
+// rather than a handful.  Each bin's run is then appended to the
 // workgroup's own region of that block with coalesced stores, so no global
 // atomics are involved.  A region that fills up sends further events to the
 // fixed-point spill rows with global atomics and flags the block.
 struct BinLds {
-  size_t stage, dst, cc, pre, lo, mt, scr, total;
+  size_t stage, dst, cc, pre, lo, mt, seg, scr, total;
 };
 __host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
   auto up = [](size_t x) { return (x + 15) / 16 * 16; };
@@ -432,12 +435,13 @@ __host__ __device__ inline BinLds bin_lds_layout(int NB, int U, bool w8) {
   // weight} with the destinations apart (8-byte records)
   L.stage = o; o = up(o + (size_t)U * kBinThreads * 8);
   L.dst = o;   o = up(o + (w8 ? (size_t)U * kBinThreads * 4 : 0));
-  // per block, two arrays used by alternate chunks: {count in the chunk,
-  // then the bin's start; records in this workgroup's region before it}
-  L.cc = o;    o = up(o + (size_t)(NB + 1) * 8 * 2);
-  L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per spike
-  L.lo = o;    o = up(o + (size_t)kBinSpikes * 8);  // segment start per spike
-  L.mt = o;    o = up(o + (size_t)kBinSpikes * 4);  // lag | inhibitory << 15
+  // per block {count in the chunk, then the bin's start; records in this
+  // workgroup's region before the chunk}, and the chunk's run lengths
+  L.cc = o;    o = up(o + (size_t)(NB + 1) * 8 + (size_t)NB * 4);
+  L.pre = o;   o = up(o + (size_t)(kBinSpikes + 1) * 8);  // event prefix per segment entry
+  L.lo = o;    o = up(o + (size_t)kBinSpikes * 8);  // table index of the batch's event 0, per entry
+  L.mt = o;    o = up(o + (size_t)kBinSpikes * 4);  // lag | inhibitory << 15 | part << 16
+  L.seg = o;   o = up(o + (size_t)kBinSegTab * 2);  // entry holding event k << sh of the batch
   L.scr = o;   o = up(o + (size_t)(kBinThreads / 64 + 2) * 8);
   L.total = o;
   return L;
@@ -457,10 +461,14 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   const BinLds Lo = bin_lds_layout(NB, U, W8);
   uint2* stage2 = (uint2*)(lds_raw + Lo.stage);
   uint32_t* dst = (uint32_t*)(lds_raw + Lo.dst);
-  uint2* const cc_arr = (uint2*)(lds_raw + Lo.cc);  // [2][NB + 1]
+  uint2* const cc = (uint2*)(lds_raw + Lo.cc);              // [NB + 1]
+  uint32_t* const runs = (uint32_t*)(lds_raw + Lo.cc + (size_t)(NB + 1) * 8);  // [NB]
+  __shared__ int s_bl, s_bh;       // block range of the chunk
+  __shared__ uint32_t s_nchunk;    // events of the chunk
   unsigned long long* pre = (unsigned long long*)(lds_raw + Lo.pre);
   unsigned long long* lo = (unsigned long long*)(lds_raw + Lo.lo);
   uint32_t* mt = (uint32_t*)(lds_raw + Lo.mt);
+  uint16_t* seg = (uint16_t*)(lds_raw + Lo.seg);
   unsigned long long* scr64 = (unsigned long long*)(lds_raw + Lo.scr);
   uint32_t* scr32 = (uint32_t*)(lds_raw + Lo.scr);
 
@@ -468,8 +476,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   if (total > a.in_cap) total = a.in_cap;  // overflow is flagged by the writer
   if (total < 0) total = 0;
   const int64_t s_lo = total * p / P, s_hi = total * (p + 1) / P;
-  for (int i = tid; i < 2 * (NB + 1); i += kBinThreads) cc_arr[i] = make_uint2(0u, 0u);
-  int par = 0;  // counter array of the next chunk
+  for (int i = tid; i < NB + 1; i += kBinThreads) cc[i] = make_uint2(0u, 0u);
   unsigned long long ev = 0;
   const int tbits = a.tbits, H = a.H;
   const uint32_t tmask = (1u << tbits) - 1u;
@@ -478,31 +485,45 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
   const uint32_t area = (uint32_t)P * (uint32_t)cap;     // records per block
 
   // every spike has H segments, one per target part: the share walks its
-  // spikes' (spike, part) segment entries
-  for (int64_t sb = s_lo * H; sb < s_hi * H; sb += kBinSpikes) {
-    const int ns = (int)((s_hi * H - sb) < kBinSpikes ? (s_hi * H - sb) : kBinSpikes);
+  // spikes' (spike, part) segment entries part by part, so that a chunk's
+  // events fall into the few blocks of one part and each block's run is
+  // long
+  const int64_t nsp = s_hi - s_lo;
+  for (int64_t sb = 0; sb < nsp * H; sb += kBinSpikes) {
+    const int ns = (int)((nsp * H - sb) < kBinSpikes ? (nsp * H - sb) : kBinSpikes);
     // (1) every thread resolves one segment entry
-    unsigned long long len = 0;
+    unsigned long long len = 0, l0 = 0;
     if (tid < ns) {
       const int64_t se = sb + tid;
-      const int64_t i = se / H;
-      const uint32_t part = (uint32_t)(se - i * H);
+      const int64_t pe = se / nsp;
+      const int64_t i = s_lo + (se - pe * nsp);
+      const uint32_t part = (uint32_t)pe;
       const uint32_t ent = a.in_list[i];
       const uint32_t src = ent >> 5;
       const uint32_t lag = ent & 31u;
-      unsigned long long l0 = 0;
       if ((int)lag < a.Dmin && (int64_t)src < a.n_src) {
         l0 = a.row[(int64_t)src * H + part];
         len = a.row[(int64_t)src * H + part + 1] - l0;
       } else if (part == 0) {
         atomicOr(a.overflow, 4);
       }
-      lo[tid] = l0;
       mt[tid] = lag | (((int64_t)src >= a.src_e_end) ? 0x8000u : 0u) | (part << 16);
     }
     unsigned long long n_batch;
     const unsigned long long ex = block_excl_scan1<unsigned long long>(len, scr64, n_batch);
-    if (tid < ns) pre[tid] = ex;
+    // event f of the batch is table entry lo[s] + f of the segment entry s
+    // holding it; seg[k] names the entry holding event k << sh, with sh >= 6
+    // the smallest that keeps the table within kBinSegTab entries (the 64
+    // events of one wave's slot share a table entry)
+    int sh = 6;
+    while (((n_batch + (1ull << sh) - 1) >> sh) > (unsigned long long)kBinSegTab) ++sh;
+    if (tid < ns) {
+      pre[tid] = ex;
+      lo[tid] = l0 - ex;
+      const unsigned long long g = (1ull << sh) - 1;
+      for (unsigned long long k = (ex + g) >> sh; k < ((ex + len + g) >> sh); ++k)
+        seg[k] = (uint16_t)tid;
+    }
     if (tid == 0) pre[ns] = n_batch;
     ev += n_batch;  // the same value in every thread; thread 0 reports it
     __syncthreads();
@@ -515,54 +536,57 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
     // previous chunk's write-out.
     const unsigned long long E_c = (unsigned long long)U * kBinThreads;
     constexpr int UM = W8 ? kBinMaxU8 : kBinMaxU;  // register budget
-    uint32_t tdk[UM], wbr[UM], rec8[W8 ? UM : 1], m4[UM / 4];
+    uint32_t tdk[UM], wbr[UM], rec8[W8 ? UM : 1], m4[UM / 2];
     auto issue = [&](unsigned long long f0) {
       const unsigned long long left = n_batch - f0;
       const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
-      // spike of this thread's first event: the last one starting at or
-      // before it (pre[ns] = n_batch lies past every event)
-      int sp = 0;
-      {
-        const unsigned long long f = f0 + (unsigned long long)tid;
-        int l = 0, h = ns;
-        while (h - l > 1) {
-          const int m = (l + h) >> 1;
-          if (pre[m] <= f) l = m;
-          else h = m;
+#pragma unroll
+      for (int u = 0; u < UM / 2; ++u) m4[u] = 0u;
+      // kBinGrp events at a time: their segment entries from the lookup
+      // table, then the entries' table offsets, ends and meta words (two LDS
+      // round trips for the group); a lane whose event lies past its table
+      // entry's segment moves on (a wave slot crosses a segment's end with
+      // probability ~64 / segment length)
+#pragma unroll
+      for (int h = 0; h < UM; h += kBinGrp) {
+        int sp[kBinGrp];
+#pragma unroll
+        for (int u = h; u < h + kBinGrp; ++u) {
+          const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+          sp[u - h] = (u < U && fr < n_ev) ? (int)seg[(f0 + fr) >> sh] : 0;
         }
-        sp = l;
-      }
+        unsigned long long l0[kBinGrp], p1[kBinGrp];
+        uint32_t m[kBinGrp];
 #pragma unroll
-      for (int u = 0; u < UM / 4; ++u) m4[u] = 0u;
+        for (int u = h; u < h + kBinGrp; ++u) {
+          l0[u - h] = lo[sp[u - h]];
+          p1[u - h] = pre[sp[u - h] + 1];
+          m[u - h] = mt[sp[u - h]];
+        }
 #pragma unroll
-      for (int u = 0; u < UM; ++u) {
-        const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
-        tdk[u] = 0u;
-        wbr[u] = 0u;
-        if (u < U && fr < n_ev) {
-          const unsigned long long f = f0 + fr;
-          // the spike's bounds, segment start and meta word are read
-          // together: one LDS round trip per event, one more per row
-          // boundary crossed
-          unsigned long long p0, p1, l0;
-          uint32_t m;
-          for (;;) {
-            p0 = pre[sp];
-            p1 = pre[sp + 1];
-            l0 = lo[sp];
-            m = mt[sp];
-            // keeps the three reads in the loop (the compiler would move
-            // them after it, behind a second wait)
-            asm volatile("" : "+v"(p0), "+v"(l0), "+v"(m));
-            if (p1 > f) break;
-            ++sp;
+        for (int u = h; u < h + kBinGrp; ++u) {
+          const uint32_t fr = (uint32_t)(u * kBinThreads + tid);
+          tdk[u] = 0u;
+          wbr[u] = 0u;
+          if (u < U && fr < n_ev) {
+            const unsigned long long f = f0 + fr;
+            int s = sp[u - h];
+            unsigned long long b0 = l0[u - h], e1 = p1[u - h];
+            uint32_t mm = m[u - h];
+            while (e1 <= f) {  // pre[ns] = n_batch lies past every event
+              ++s;
+              b0 = lo[s];
+              e1 = pre[s + 1];
+              mm = mt[s];
+            }
+            const unsigned long long e = b0 + f;
+            tdk[u] = a.tw[e];
+            if constexpr (W8) wbr[u] = ((const uint32_t*)a.wbits)[e];
+            else wbr[u] = ((const uint8_t*)a.wbits)[e];
+            // lag | inh << 5 | part << 6 (16 bits per event)
+            m4[u >> 1] |= ((mm & 31u) | ((mm >> 10) & 32u) | (((mm >> 16) & 63u) << 6))
+                          << ((u & 1) * 16);
           }
-          const unsigned long long e = l0 + (f - p0);
-          tdk[u] = a.tw[e];
-          if constexpr (W8) wbr[u] = ((const uint32_t*)a.wbits)[e];
-          else wbr[u] = ((const uint8_t*)a.wbits)[e];
-          // lag | inh << 5 | part << 6
-          m4[u >> 2] |= ((m & 31u) | ((m >> 10) & 32u) | (((m >> 16) & 3u) << 6)) << ((u & 3) * 8);
         }
       }
     };
@@ -570,10 +594,21 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
     for (unsigned long long f0 = 0; f0 < n_batch; f0 += E_c) {
       const unsigned long long left = n_batch - f0;
       const uint32_t n_ev = left < E_c ? (uint32_t)left : (uint32_t)E_c;
-      // this chunk's counters, and the previous chunk's (its starts and the
-      // fills before it; zero before the first chunk)
-      uint2* const cc = cc_arr + (par ? NB + 1 : 0);
-      uint2* const cp = cc_arr + (par ? 0 : NB + 1);
+      // the chunk's blocks: those of the parts of its first and last events
+      // (segments are ordered by part, so every event lies in between)
+      if (tid == 0) {
+        int pr[2];
+        for (int k = 0; k < 2; ++k) {
+          const unsigned long long f = f0 + (k ? n_ev - 1 : 0);
+          int sq = (int)seg[f >> sh];
+          while (pre[sq + 1] <= f) ++sq;
+          pr[k] = (int)((mt[sq] >> 16) & 63u);
+        }
+        const int64_t bl = ((int64_t)pr[0] << tbits) / B;
+        const int64_t bh = ((((int64_t)pr[1] + 1) << tbits) - 1) / B;
+        s_bl = (int)bl;
+        s_bh = (int)(bh < NB - 1 ? bh : NB - 1);
+      }
       // classify: tdk[u] becomes the event's key (block << 16 | rank in the
       // block's bin), wbr[u] (4-byte form) or rec8[u] (FP32) its record
       // Eight events at a time: their rank atomics are all issued before
@@ -595,7 +630,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           rk[u - h] = 0u;
           if constexpr (W8) rec8[u] = 0u;
           if (u < U && fr < n_ev) {
-            const uint32_t m = (m4[u >> 2] >> ((u & 3) * 8)) & 255u;
+            const uint32_t m = (m4[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
             const int tgt = (int)(((m >> 6) << tbits) | (td & tmask));
             // block = tgt / B from an FP32 estimate, corrected by one step
             int blk = (int)((float)tgt * inv_B);
@@ -616,30 +651,24 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
           if (tdk[u] != 0xffffffffu) tdk[u] |= rk[u - h];
       }
       __syncthreads();
-      // (3) bin starts: exclusive scan of the counts, in place.  The same
-      // pass advances the regions' fills by the previous chunk's runs (its
-      // starts' differences) and, once every thread has read them, clears
-      // the previous chunk's counters for the next chunk.
+      // (3) bin starts: exclusive scan of the counts of the chunk's blocks,
+      // in place; the runs are kept for the fills
+      const int bl = s_bl, bh = s_bh;
       {
-        const int per = (NB + kBinThreads - 1) / kBinThreads;
-        const int i0 = tid * per, i1 = (i0 + per) < NB ? i0 + per : NB;
+        const int nr = bh - bl + 1;
+        const int per = (nr + kBinThreads - 1) / kBinThreads;
+        const int i0 = bl + tid * per, i1 = (i0 + per) < bh + 1 ? i0 + per : bh + 1;
         uint32_t sum = 0;
-        for (int i = i0; i < i1; ++i) {
-          sum += cc[i].x;
-          cc[i].y = cp[i].y + (cp[i + 1].x - cp[i].x);
-        }
+        for (int i = i0; i < i1; ++i) sum += cc[i].x;
         uint32_t n_chunk;
         uint32_t run = block_excl_scan1<uint32_t>(sum, scr32, n_chunk);
         for (int i = i0; i < i1; ++i) {
           const uint32_t c = cc[i].x;
+          runs[i] = c;
           cc[i].x = run;
           run += c;
-          cp[i].x = 0u;
         }
-        if (tid == 0) {
-          cc[NB].x = n_chunk;
-          cp[NB].x = 0u;
-        }
+        if (tid == 0) s_nchunk = n_chunk;
       }
       __syncthreads();
       // (4) scatter into bin order, with each record's destination: its
@@ -679,7 +708,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       // would be reloaded, and waited for, before every store, since the
       // stores might alias it); events of full regions are added in a
       // separate, rarely taken pass.
-      const uint32_t n_chunk = cc[NB].x;
+      const uint32_t n_chunk = s_nchunk;
+      // the regions' fills advance by this chunk's runs; counts clear for
+      // the next chunk (the scatter, which read the fills, is behind the
+      // barrier above)
+      {
+        const int nr = bh - bl + 1;
+        for (int i = bl + tid; i < bl + nr; i += kBinThreads) {
+          cc[i].y += runs[i];
+          cc[i].x = 0u;
+        }
+      }
       {
         void* const bins = a.bins;
         bool spill = false;
@@ -738,18 +777,15 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(BinArgs args) {
       // issued after this chunk's stores: the classify's first wait for a
       // load also waits for every store issued before it.
       if (f0 + E_c < n_batch) issue(f0 + E_c);
-      // no barrier: the next chunk's counters were cleared before this
-      // chunk's scatter, and its scatter overwrites the stage only after two
-      // more barriers
-      par ^= 1;
+      // the next chunk's counts start from the zeros written above
+      __syncthreads();
     }
   }
   // record counts of this workgroup's regions: the last chunk's fills plus
   // its runs (all zero if there was no chunk)
   {
-    const uint2* const cl = cc_arr + (par ? 0 : NB + 1);
     for (int b = tid; b < NB; b += kBinThreads) {
-      const uint32_t f = cl[b].y + (cl[b + 1].x - cl[b].x);
+      const uint32_t f = cc[b].y;
       a.bin_cnt[(size_t)b * P + p] = f < (uint32_t)cap ? f : (uint32_t)cap;
     }
   }
