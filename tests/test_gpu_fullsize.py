@@ -66,6 +66,9 @@ def _check_cells(got, exp, absw, tol=1e-6):
 # brain-scale share
 # --------------------------------------------------------------------------
 SHARE_LO, SHARE_HI = 517_000, 517_448
+# further samples: across the boundary of the first two target parts of
+# 2^18 (its block gets records of both parts) and the last, ragged block
+SHARE_EDGES = [(262_144 - 224, 262_144 + 224), (1_125_000 - 448, 1_125_000)]
 
 
 def test_brain_share_one_slice_with_weights():
@@ -75,7 +78,10 @@ def test_brain_share_one_slice_with_weights():
     net.prepare_input(20)
     net.simulate_steps(10)
     net.deliver()                      # the first input slice, window [10, 30)
-    got = net.ring(20)[:, SHARE_LO:SHARE_HI]
+    ring = net.ring(20)
+    samples = [(SHARE_LO, SHARE_HI)] + SHARE_EDGES
+    got = {s: ring[:, s[0]:s[1]].copy() for s in samples}
+    del ring
     assert net.stats()["overflow"] == 0
     net.close()
     del net
@@ -83,19 +89,21 @@ def test_brain_share_one_slice_with_weights():
     src, lag = oracle.open_loop_spikes(cfg, 0, 10, cap=1 << 20)
     L = cfg["ring_len"]
     rows = [(10 + s) % L for s in range(20)]
-    # the oracle decoding the stored BF16 residuals: per-cell FP32 bound
-    ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=SHARE_LO,
-                          tgt_hi=SHARE_HI))
-    ref.deliver(src, lag, 0)
-    exp = ref.ring()[rows]
-    absw = _abs_sum(ref, src, lag, 0, SHARE_LO, 10, 20, L)
-    assert absw.sum() > 0
-    _check_cells(got, exp, absw)
+    for lo, hi in samples:
+        # the oracle decoding the stored BF16 residuals: per-cell FP32 bound
+        ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=lo, tgt_hi=hi))
+        ref.deliver(src, lag, 0)
+        exp = ref.ring()[rows]
+        absw = _abs_sum(ref, src, lag, 0, lo, 10, 20, L)
+        assert absw.sum() > 0
+        _check_cells(got[(lo, hi)], exp, absw)
+        del ref
     # the oracle holding the FP32 table weights: the BF16 form's error
     ref32 = oracle.Net(dict(cfg, wform=0, tgt_lo=SHARE_LO, tgt_hi=SHARE_HI))
     ref32.deliver(src, lag, 0)
     exact = ref32.ring()[rows]
-    normwise = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+    g = got[(SHARE_LO, SHARE_HI)]
+    normwise = np.linalg.norm(g - exact) / np.linalg.norm(exact)
     assert normwise <= 1e-3, normwise
 
 

@@ -185,10 +185,17 @@ def test_open_loop_counts_exact(layout):
     assert net.stats()["spikes_delivered"] == len(src)
 
 
+# Target samples of the brain-scale share: across the boundary of the first
+# two target parts of 2^18 (its block gets records of both parts), inside a
+# part, and the last, ragged block (1,125,000 = 1,255 * 896 + 520).
+SHARE_SAMPLES = [(262_144 - 224, 262_144 + 224), (517_000, 517_448), (1_125_000 - 448, 1_125_000)]
+
+
 def test_brain_share_full_size_sample():
     """The one-GPU share of the brain-scale net at full size (1,125,000
     targets, 10M virtual sources, 1.27e10 synapses): one input slice in
-    count mode, compared cell by cell with the oracle on 448 targets."""
+    count mode, compared cell by cell with the oracle on three samples of
+    448 targets."""
     cfg = dict(W.ALPHA_BRAIN_SHARE)
     net = sdeliver.Net(cfg).build()
     assert net.n_syn == 1125000 * 11250
@@ -198,16 +205,16 @@ def test_brain_share_full_size_sample():
     net.simulate_steps(10)
     net.deliver()
     got = net.ring(20)
-    lo, hi = 517_000, 517_448
-    ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=lo, tgt_hi=hi))
     src, lag = oracle.open_loop_spikes(cfg, 0, 10, cap=1 << 20)
     assert 60_000 < len(src) < 100_000
-    ref.deliver(src, lag, 0)
     L = cfg["ring_len"]
-    exp = ref.counts()[[(10 + s) % L for s in range(20)]]
-    assert np.array_equal(got[:, lo:hi].astype(np.int64), exp.astype(np.int64))
-    # every synapse of every input spike was delivered
-    out_w, out_deg = ref.out_weight()
+    for lo, hi in SHARE_SAMPLES:
+        ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=lo, tgt_hi=hi))
+        ref.deliver(src, lag, 0)
+        exp = ref.counts()[[(10 + s) % L for s in range(20)]]
+        assert np.array_equal(got[:, lo:hi].astype(np.int64), exp.astype(np.int64)), (lo, hi)
+        del ref
+    # every input spike was delivered
     st = net.stats()
     assert st["spikes_delivered"] == len(src)
     assert st["overflow"] == 0
