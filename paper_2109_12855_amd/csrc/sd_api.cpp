@@ -1279,7 +1279,7 @@ sd_status run_persistent(sd_ctx* c, int32_t S) {
   a.in_cap = c->list_cap;
   a.zero_cnt = nullptr;
   const int32_t pend0 = c->pend_open ? 1 : 0;
-  HIP_TRY(c, hipMemsetAsync(c->pbar, 0, 4, c->stream));
+  HIP_TRY(c, launch_set_word(c->stream, c->pbar, 0u));  // the grid barrier's arrival counter
   HIP_TRY(c, launch_persist(c->stream, a, c->list, c->cnt3, c->cur, c->ci, pend0, S, c->t_now,
                             c->rb_hi, c->pbar, c->lau.lds, g.wform));
   for (int32_t k = 0; k < S; ++k) {

@@ -221,6 +221,7 @@ hipError_t launch_fill_sm(hipStream_t s, const BuildArgs& a);
 hipError_t launch_bin(hipStream_t s, const BinArgs& a, int32_t P, size_t lds, bool w8);
 hipError_t launch_zero_rows(hipStream_t s, float* rb, int64_t N, int32_t L, int64_t t_lo,
                             int64_t t_hi);
+hipError_t launch_set_word(hipStream_t s, unsigned* p, unsigned v);
 // pack and validate an external spike list (see k_pack_list); cnt receives n
 hipError_t launch_pack_list(hipStream_t s, const uint32_t* src, const uint8_t* lag, int64_t n,
                             int64_t n_src, int32_t Dmin, uint32_t* out, int32_t* cnt,

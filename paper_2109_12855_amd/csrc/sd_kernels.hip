@@ -8,15 +8,19 @@
 //   block's ring window (d_max rows x B neurons, 64-bit fixed point), then
 //   advances its neurons through the next slice with the exact propagators
 //   (Sec. 2.1), reading inputs straight from the LDS window, and finally
-//   compacts the new spikes with a bitmask + block scan and appends them,
-//   ordered (lag, neuron) within the block, to the slice's contiguous spike
-//   list.  Rows of the window that are due in later slices are written to
-//   the ring in HBM by the threads without a neuron, during the update.
+//   compacts the new spikes (each wave's ballot of a step kept as two mask
+//   words, then a block scan of their bit counts) and appends them, ordered
+//   (lag, neuron) within the block, to the slice's contiguous spike list.
+//   Rows of the window that are due in later slices are written to the ring
+//   in HBM by the threads without a neuron, during the update.
 //   Source-major layout: k_bin first sorts the slice's events by target
-//   block into binned records; the slice kernel then accumulates those
-//   instead of walking segments (k_slice1<form, true, dyn>).
+//   block into binned records, walking its spikes' rows one target part at
+//   a time; the slice kernel then accumulates those instead of walking
+//   segments (k_slice1<form, true, dyn>).
 //   k_shift_args moves the device-resident arguments of a captured batch
-//   graph on by one period.
+//   graph on by one period.  k_persist (opt-in) runs several slices in one
+//   cooperative launch, each block's ring window kept in LDS across them,
+//   with grid barriers between slices.
 //
 // Build (once, untimed, Sec. 2.2):
 //   k_count / scan / k_fill lay out the block-major table: segment (src, b)
@@ -2126,6 +2130,10 @@ __global__ void k_zero_rows(float* rb, int64_t N, int32_t L, int64_t t_lo, int64
   }
 }
 
+// One word set by a one-thread kernel: a clear issued on a stream that a
+// caller may be capturing becomes a kernel node rather than a memset node.
+__global__ void k_set_word(unsigned* p, unsigned v) { *p = v; }
+
 // An external spike list (separate source and lag arrays) packed into the
 // delivery's entry format (src << 5 | lag), validated on the device: an
 // entry with src >= n_src or lag >= d_min becomes kBadEntry (delivers
@@ -2401,6 +2409,11 @@ __global__ void k_shift_args(SliceArgs* args, int32_t n, int64_t shift) {
 
 hipError_t launch_shift_args(hipStream_t s, SliceArgs* args, int32_t n, int64_t shift) {
   hipLaunchKernelGGL(k_shift_args, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, args, n, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_word(hipStream_t s, unsigned* p, unsigned v) {
+  hipLaunchKernelGGL(k_set_word, dim3(1), dim3(1), 0, s, p, v);
   return hipGetLastError();
 }
 
