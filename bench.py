@@ -534,7 +534,7 @@ def cpu_paper_algorithms(slices: int = 30, threads: int | None = None) -> dict:
                        "delivery only",
            "threads": net.n_threads, "synapses": net.n_synapses, "build_s": round(build_s, 1),
            "spikes_per_slice": spikes, "slices": slices, "b_ts": 16, "b_rb": 16}
-    # ring buffers packed back to back (this build's layout), then inside
+    # ring buffers packed back to back (the GPU path's layout), then inside
     # 1 KB neuron objects (stride 128 cells), as in the simulator the paper
     # studies, where the ring-buffer accesses miss the caches
     for layout, stride in (("packed", base["ring_len"]), ("objects_1kb", 128)):
@@ -592,7 +592,7 @@ def main():
                          "then holds those legs alone)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

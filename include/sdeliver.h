@@ -46,7 +46,7 @@ typedef enum {
   SD_EHIP = -3,          /* a HIP runtime call failed                        */
   SD_EOVERFLOW = -4,     /* a device-side capacity was exceeded (sticky)     */
   SD_ESTATE = -5,        /* call not valid in the context's current state    */
-  SD_EUNSUPPORTED = -6   /* configuration outside what this build supports   */
+  SD_EUNSUPPORTED = -6   /* configuration outside what the library supports */
 } sd_status;
 
 typedef enum { SD_IAF_PSC_DELTA = 0, SD_IAF_PSC_ALPHA = 1 } sd_model;
