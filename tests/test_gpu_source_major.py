@@ -53,6 +53,34 @@ def test_replay_delivery(case):
     _replay_check(cfg, src, lag)
 
 
+# 300,000 targets: more than one target part (parts hold at most 2^18
+# targets), a block straddling the parts' boundary, and at in-degree 10 most
+# (spike, part) segments hold zero or one synapse.
+TWO_PARTS = W.tiny(model=1, n=300_000, k=10, seed=12, d_lo=10, d_hi=20)
+
+
+def test_two_target_parts_replay():
+    """Counts exact, weights within 1e-6 sum|w| per cell and every event
+    delivered, for 30,000 replayed spikes, against the full oracle."""
+    cfg = dict(TWO_PARTS, layout=SM)
+    n = cfg["n_exc"] + cfg["n_inh"]
+    src, lag = W.replay_spikes(n, 30_000, cfg["d_min"], seed=13)
+    _replay_check(cfg, src, lag)
+
+
+def test_two_target_parts_closed_loop():
+    cfg = dict(TWO_PARTS, record_spikes=1, layout=SM)
+    net = sdeliver.Net(cfg).build()
+    ras = []
+    eps, t_bad, n_cmp, _ = spike_exact(cfg, net, lambda: oracle.Net(cfg), horizon=300,
+                                       min_exact=30, raster=ras)
+    assert n_cmp > 1000, n_cmp
+    # spikes on both sides of the parts' boundary
+    idx = ras[0][1]
+    assert (idx < (1 << 18)).any() and (idx >= (1 << 18)).any()
+    assert net.stats()["overflow"] == 0
+
+
 @pytest.mark.parametrize("case", [0, 1, 3])
 def test_closed_loop_tiny(case):
     cfg = dict(_tiny_cases()[case], record_spikes=1, layout=SM)
