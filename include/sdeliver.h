@@ -253,6 +253,14 @@ sd_status sd_set_count_mode(sd_ctx* ctx, int32_t on);
  * are then invalid). */
 sd_status sd_set_persistent(sd_ctx* ctx, int32_t max_slices);
 
+/* For callers that watch a persistent run (and for tests of its failure
+ * path): the most polls a grid barrier of a persistent launch makes while
+ * it waits for the other workgroups before it gives up, setting bit 4 of
+ * sd_stats.overflow and ending the launch early.  polls < 0 restores the
+ * default of 2^22 polls; 0 makes the first workgroup to reach a barrier give
+ * up at once.  SD_EINVAL for a null context. */
+sd_status sd_set_barrier_spin(sd_ctx* ctx, int64_t polls);
+
 /* Open loop: precompute the virtual sources' spikes for steps
  * [t_now, t_now + n_steps) (outside any timed region). */
 sd_status sd_prepare_input(sd_ctx* ctx, int64_t n_steps);

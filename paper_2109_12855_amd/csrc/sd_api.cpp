@@ -300,6 +300,7 @@ struct sd_ctx {
   SliceLauncher lau;        // this network alone
   int32_t persist = 0;      // slices per persistent launch (0: one launch per slice)
   unsigned* pbar = nullptr; // grid-barrier arrivals of a persistent launch
+  int64_t bar_spin = -1;    // polls before a grid barrier gives up (< 0: default)
 };
 
 // Independent networks advanced together: every slice of all members is
@@ -1281,7 +1282,7 @@ sd_status run_persistent(sd_ctx* c, int32_t S) {
   const int32_t pend0 = c->pend_open ? 1 : 0;
   HIP_TRY(c, launch_set_word(c->stream, c->pbar, 0u));  // the grid barrier's arrival counter
   HIP_TRY(c, launch_persist(c->stream, a, c->list, c->cnt3, c->cur, c->ci, pend0, S, c->t_now,
-                            c->rb_hi, c->pbar, c->lau.lds, g.wform));
+                            c->rb_hi, c->pbar, c->bar_spin, c->lau.lds, g.wform));
   for (int32_t k = 0; k < S; ++k) {
     if (k > 0 || pend0) c->rb_hi = std::max(c->rb_hi, c->t_now + g.d_max);
     c->cur ^= 1;
@@ -1321,6 +1322,12 @@ sd_status sd_set_persistent(sd_ctx* c, int32_t max_slices) {
     return fail(c, SD_EUNSUPPORTED, "persistent slices need all %lld blocks resident at once "
                 "(%d per CU on %d CUs)", (long long)grid, occ, n_cu);
   c->persist = max_slices;
+  return SD_OK;
+}
+
+sd_status sd_set_barrier_spin(sd_ctx* c, int64_t polls) {
+  if (!c) return SD_EINVAL;
+  c->bar_spin = polls < 0 ? -1 : polls;
   return SD_OK;
 }
 

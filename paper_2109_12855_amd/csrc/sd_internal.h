@@ -210,7 +210,8 @@ hipError_t launch_slice1(hipStream_t s, const SliceArgs& a, size_t lds, int wfor
 int persist_occupancy(int wform, size_t lds);
 hipError_t launch_persist(hipStream_t s, const SliceArgs& a, uint32_t* const lists[2],
                           int32_t* cnt3, int32_t cur0, int32_t ci0, int32_t pend0, int32_t S,
-                          int64_t t0, int64_t rb_hi0, unsigned* bar, size_t lds, int wform);
+                          int64_t t0, int64_t rb_hi0, unsigned* bar, int64_t spin_limit,
+                          size_t lds, int wform);
 size_t slice_lds_bytes(int B, int Dmin, int win_rows, bool plastic = false, bool bin = false);
 // add shift to the time fields (t_upd, t_slice0, w_lo, rb_hi) of args[0..n)
 hipError_t launch_shift_args(hipStream_t s, SliceArgs* args, int32_t n, int64_t shift);

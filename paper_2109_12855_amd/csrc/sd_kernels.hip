@@ -1791,19 +1791,20 @@ __global__ void __launch_bounds__(kSliceThreads) k_slice1(SingleArgs s) {
 // registers.  Slices are separated by a grid barrier, since the spike list
 // one slice writes is read by every block in the next; the lists and their
 // three rotating counters are those of the one-launch-per-slice path.
-constexpr long kBarSpin = 1L << 22;  // polls before a grid barrier gives up
+constexpr int64_t kBarSpin = 1LL << 22;  // default polls before a grid barrier gives up
 
 // All workgroups of the launch wait here; the release fence publishes this
 // workgroup's global writes (spike list, counters) and the acquire fence
-// drops stale lines of other workgroups' writes.  A wait past kBarSpin polls
+// drops stale lines of other workgroups' writes.  A wait past spin_limit polls
 // sets bit 4 of the overflow flags, and every workgroup then leaves.
-__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* overflow) {
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* overflow,
+                             int64_t spin_limit) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
+    int64_t spins = 0;
     int ok = 1;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
@@ -1812,7 +1813,7 @@ __device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* overflow) 
         ok = 0;
         break;
       }
-      if (spins > kBarSpin) {
+      if (spins > spin_limit) {
         atomicOr(overflow, 16);
         ok = 0;
         break;
@@ -1836,6 +1837,7 @@ struct PersistArgs {
   int64_t t0;          // first step of slice 0
   int64_t rb_hi0;      // HBM ring rows of steps below this hold earlier sums
   unsigned* bar;       // grid-barrier arrivals (zero at launch)
+  int64_t spin_limit;  // polls before a grid barrier gives up
 };
 
 template <int WF>
@@ -2088,7 +2090,9 @@ __global__ void __launch_bounds__(kSliceThreads) k_persist(PersistArgs p) {
     }
     cur ^= 1;
     ci = (ci + 1) % 3;
-    if (k + 1 < S) ok = grid_barrier(pp->bar, (unsigned)gridDim.x * (unsigned)(k + 1), a.overflow);
+    if (k + 1 < S)
+      ok = grid_barrier(pp->bar, (unsigned)gridDim.x * (unsigned)(k + 1), a.overflow,
+                        pp->spin_limit);
   }
   if (!live) return;
   // ---- rows due after the last slice go to the HBM ring ---------------------
@@ -2372,7 +2376,8 @@ int persist_occupancy(int wform, size_t lds) {
 // once, so the grid barriers cannot wait on a workgroup that never starts.
 hipError_t launch_persist(hipStream_t s, const SliceArgs& a, uint32_t* const lists[2],
                           int32_t* cnt3, int32_t cur0, int32_t ci0, int32_t pend0, int32_t S,
-                          int64_t t0, int64_t rb_hi0, unsigned* bar, size_t lds, int wform) {
+                          int64_t t0, int64_t rb_hi0, unsigned* bar, int64_t spin_limit,
+                          size_t lds, int wform) {
   PersistArgs p;
   p.a = a;
   p.lists[0] = lists[0];
@@ -2386,6 +2391,7 @@ hipError_t launch_persist(hipStream_t s, const SliceArgs& a, uint32_t* const lis
   p.t0 = t0;
   p.rb_hi0 = rb_hi0;
   p.bar = bar;
+  p.spin_limit = spin_limit < 0 ? kBarSpin : spin_limit;
   void* args[] = {&p};
   const dim3 grid((unsigned)(8 * p.per_xcd)), block(kSliceThreads);
   switch (wform) {

@@ -82,7 +82,7 @@ class sd_stats(C.Structure):
 EXPORTS = (
     "sd_query_sizes", "sd_create", "sd_destroy", "sd_last_error", "sd_build_connections",
     "sd_update_neurons", "sd_deliver_spikes", "sd_deliver_pending", "sd_simulate", "sd_simulate_steps",
-    "sd_set_count_mode", "sd_set_persistent", "sd_prepare_input", "sd_t_now", "sd_get_sizes", "sd_get_stats",
+    "sd_set_count_mode", "sd_set_persistent", "sd_set_barrier_spin", "sd_prepare_input", "sd_t_now", "sd_get_sizes", "sd_get_stats",
     "sd_read_ring", "sd_read_state", "sd_write_state", "sd_get_spikes", "sd_get_pending",
     "sd_export_connections", "sd_export_segments", "sd_export_block", "sd_get_tables",
     "sd_host_tables", "sd_batch_create", "sd_batch_destroy", "sd_batch_last_error",
@@ -117,6 +117,7 @@ def lib():
         "sd_simulate_steps": ([vp, i64], i32),
         "sd_set_count_mode": ([vp, i32], i32),
         "sd_set_persistent": ([vp, i32], i32),
+        "sd_set_barrier_spin": ([vp, i64], i32),
         "sd_prepare_input": ([vp, i64], i32),
         "sd_t_now": ([vp], i64),
         "sd_get_sizes": ([vp, P(sd_sizes)], i32),
@@ -311,6 +312,11 @@ class Net:
         """Run up to max_slices whole slices per persistent launch (0: one
         launch per slice)."""
         self._check(lib().sd_set_persistent(self._h, int(max_slices)), "sd_set_persistent")
+
+    def set_barrier_spin(self, polls: int):
+        """Polls a persistent launch's grid barrier waits before it gives up
+        (overflow bit 16); < 0 restores the default."""
+        self._check(lib().sd_set_barrier_spin(self._h, int(polls)), "sd_set_barrier_spin")
 
     # -- read-back --------------------------------------------------------------
     @property

@@ -157,3 +157,24 @@ def test_rejects_ineligible_nets():
         assert e.value.status == sdeliver.SD_EUNSUPPORTED, cfg.get("name")
         net.set_persistent(0)  # always accepted
         net.close()
+
+
+def test_barrier_timeout_ends_launch():
+    """The timeout path of the grid barrier, forced from the host: with no
+    polls allowed, the first workgroup to reach a barrier gives up, every
+    workgroup leaves the launch (none waits), and bit 4 of the overflow
+    flags reports it; the default limit then runs clean again."""
+    cfg = NETS["delta_1000"]
+    net = sdeliver.Net(cfg).build()
+    net.set_persistent(8)
+    net.set_barrier_spin(0)
+    net.simulate_steps(8 * cfg["d_min"])
+    assert net.stats()["overflow"] & 16
+    net.close()
+    net = sdeliver.Net(cfg).build()
+    net.set_persistent(8)
+    net.set_barrier_spin(0)
+    net.set_barrier_spin(-1)
+    net.simulate_steps(8 * cfg["d_min"])
+    assert net.stats()["overflow"] == 0
+    net.close()
