@@ -1,8 +1,9 @@
 """Oracle parity at the benchmark networks' full sizes, with weights.
 
 * The brain-scale share (1,125,000 targets, 10M virtual sources, 1.27e10
-  synapses): one input slice with weights on a target sample, cell by cell
-  within 1e-6 * sum|w| of the oracle decoding the same BF16 residuals, and
+  synapses): one input slice with weights on target samples, cell by cell
+  within 1e-6 * sum|w| of the oracle decoding the same BF16 residuals (and,
+  for the FP32 form, of the oracle holding the same FP32 weights), and
   within 1e-3 normwise of the oracle holding the FP32 table weights; then an
   open-loop run whose sample raster is spike-exact over 50 ms (the sample's
   dynamics do not depend on the other targets in open loop).
@@ -71,8 +72,13 @@ SHARE_LO, SHARE_HI = 517_000, 517_448
 SHARE_EDGES = [(262_144 - 224, 262_144 + 224), (1_125_000 - 448, 1_125_000)]
 
 
-def test_brain_share_one_slice_with_weights():
-    cfg = dict(W.ALPHA_BRAIN_SHARE)
+@pytest.mark.parametrize("wform", [2, 0])
+def test_brain_share_one_slice_with_weights(wform):
+    """Residual BF16 (the headline form, 5 B per synapse) and FP32 (8-byte
+    binned records): every cell of three target samples after one input
+    slice."""
+    name = {0: "alpha_share_1125000_fp32", 2: "alpha_share_1125000_bf16_resid"}[wform]
+    cfg = dict(W.ALPHA_BRAIN_SHARE, wform=wform, name=name)
     net = sdeliver.Net(cfg).build()
     assert net.n_syn == 1125000 * 11250
     net.prepare_input(20)
@@ -90,7 +96,8 @@ def test_brain_share_one_slice_with_weights():
     L = cfg["ring_len"]
     rows = [(10 + s) % L for s in range(20)]
     for lo, hi in samples:
-        # the oracle decoding the stored BF16 residuals: per-cell FP32 bound
+        # the oracle holding the stored weights (the BF16 residuals decoded,
+        # or the FP32 values): per-cell FP32 bound
         ref = oracle.Net(dict(cfg, wform=W.ORACLE_WFORM[cfg["wform"]], tgt_lo=lo, tgt_hi=hi))
         ref.deliver(src, lag, 0)
         exp = ref.ring()[rows]
@@ -98,6 +105,8 @@ def test_brain_share_one_slice_with_weights():
         assert absw.sum() > 0
         _check_cells(got[(lo, hi)], exp, absw)
         del ref
+    if wform == 0:
+        return
     # the oracle holding the FP32 table weights: the BF16 form's error
     ref32 = oracle.Net(dict(cfg, wform=0, tgt_lo=SHARE_LO, tgt_hi=SHARE_HI))
     ref32.deliver(src, lag, 0)
