@@ -260,3 +260,63 @@ def test_open_loop_source_rate():
     # (lag, src) order
     key = l.astype(np.int64) * 10**8 + s
     assert np.all(np.diff(key) > 0)
+
+
+# --------------------------------------------------------------------------
+# closed-loop rate against mean-field theory
+# --------------------------------------------------------------------------
+def _mean_field_rate(c: dict) -> float:
+    """Self-consistent stationary rate (Hz) of the delta-synapse balanced
+    network in the diffusion approximation (Brunel 2000, J. Comput.
+    Neurosci. 8:183, the Siegert first-passage rate of the leaky integrator
+    with Gaussian input): 1/nu = t_ref + tau_m sqrt(pi) * integral of
+    exp(u^2)(1 + erf u) = erfcx(-u) from (V_reset - mu)/sigma to
+    (V_th - mu)/sigma, where mu and sigma^2 sum J*rate*tau_m and
+    J^2*rate*tau_m over the Poisson drive and the K_E excitatory (J) and
+    K_I inhibitory (-g J) inputs firing at nu.  Written from scipy's
+    quadrature, independently of the oracle."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+    from scipy.special import erfcx
+
+    tau, t_ref = c["tau_m"] * 1e-3, c["t_ref"] * 1e-3
+    J, g, ke, ki = c["w_exc"], c["g"], c["k_exc"], c["k_inh"]
+    nu_x, jx = c["drive_rate_hz"], c["drive_w"]
+
+    def phi(nu):
+        mu = tau * (jx * nu_x + nu * (ke * J - ki * g * J))
+        sig = math.sqrt(tau * (jx * jx * nu_x + nu * (ke * J * J + ki * (g * J) ** 2)))
+        integral, _ = quad(lambda u: erfcx(-u), (c["v_reset"] - mu) / sig, (c["v_th"] - mu) / sig)
+        return 1.0 / (t_ref + tau * math.sqrt(math.pi) * integral)
+
+    return brentq(lambda nu: phi(nu) - nu, 1e-3, 1.0 / t_ref - 1e-6)
+
+
+@pytest.mark.parametrize("over", [
+    dict(g=6.0),                                              # stronger inhibition
+    dict(drive_rate_hz=2000.0),                               # weaker drive
+    dict(w_exc=0.4, drive_w=0.4, drive_rate_hz=5000.0),       # smaller jumps
+])
+def test_closed_loop_rate_matches_mean_field(over):
+    """The oracle's whole closed loop (generation, delivery, Poisson drive,
+    exact update with threshold, reset and refractoriness) against theory:
+    the population rate over [0.2, 1) s, averaged over three seeds of the
+    1,250-neuron delta net (Sec. 2.2's balanced random network), lies within
+    8% of the mean-field rate.  Measured: 0.97-1.02 of it at these points.
+    Planted in the oracle's parameters, a reset to 0 mV, 10% weaker
+    inhibition or half the membrane time constant move the ratio to
+    0.51-0.75 or 1.21-1.32 at every point, and a dropped refractory period
+    to 1.35-1.44 at the first two (feedback compensates it at the third).
+    A point where simulation and the diffusion approximation part (a
+    0.5 ms refractory period: 15% above theory) is not used.  CV has no
+    such reference and stays unpinned."""
+    from helpers import rate_cv
+
+    c = dict(W.DELTA_SMALL, **over)
+    n = c["n_exc"] + c["n_inh"]
+    rates = []
+    for seed in (1, 2, 3):
+        st, idx = oracle.Net(dict(c, seed=seed)).simulate(10000)
+        rates.append(rate_cv(st, idx, n, 2000, 10000, c["h"])[0])
+    ratio = float(np.mean(rates)) / _mean_field_rate(c)
+    assert abs(ratio - 1.0) <= 0.08, (rates, ratio)
